@@ -1,0 +1,681 @@
+// Plain FP64 CPU oracle for the weighted-upwind vector kinetic lattice
+// Boltzmann (WU-VKLB) method of Brown, Chaudhry and Shadid.
+//
+// TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the
+// benchmark's CPU-baseline leg may load this library. It shares no code,
+// header, table or helper with the HIP implementation under
+// paper_2608_04283_amd/ and neither side includes the other.
+//
+// The oracle is written to be read against the paper, not to be fast:
+//   * fluxes F^(d)(U) exactly as the paper states them
+//       shallow water  -- Sec. 5.1, shallow water system
+//       Euler          -- Sec. 5.2, Euler system + ideal-gas closure
+//       ideal MHD-GLM  -- Sec. 5.3, MHD system with divergence cleaning
+//   * the flux Jacobian is formed by complex-step differentiation of that
+//     flux (exact to rounding, no difference quotient), eigenvalues are the
+//     closed forms of each system, right eigenvectors are null vectors of
+//     (A - lambda I) (Sec. 2.2, eigen-decomposition of the flux Jacobian),
+//   * expansion coefficients Phi = P^{-1} F by an LU solve (Sec. 2.2,
+//     expansion coefficients),
+//   * sigmoid weights alpha(lambda) = 1/(1+exp(-k lambda/max_j|lambda_j|))
+//     and the weighted partial fluxes (Sec. 3.1, weighted upwind splitting),
+//   * the WU equilibrium in 1D (Sec. 3.1, f1..f3) and 2D (Sec. 3.4, D2Q5 set),
+//   * collision, streaming, moment recovery and the CFL speed update in the
+//     order of the flow chart of Sec. 3.5.
+// Readings where the paper is silent (boundary ghosts, end-time landing,
+// local lambda_max, global c_h) are listed in the design doc and noted inline.
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+using cd = std::complex<double>;
+
+enum { SYS_SW = 0, SYS_EULER = 1, SYS_MHD = 2, SYS_LINEAR = 3 };
+enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1 };
+enum { XI_CFL = 0, XI_FIXED = 1 };
+
+constexpr int PMAX = 9;
+
+}  // namespace
+
+extern "C" {
+
+// Run description shared with the Python wrapper (oracle/oracle.py mirrors it).
+typedef struct {
+  int kind;          // SYS_*
+  int dim;           // 1 or 2
+  int64_t n[2];      // cells per axis (n[1] = 1 in 1D)
+  double lo[2], hi[2];
+  double g, gamma, ch_factor;
+  double adv[2];     // linear advection speeds (test system)
+  int xi_mode;       // XI_CFL or XI_FIXED
+  double nu;         // CFL number for XI_CFL
+  double xi_fixed;   // streaming speed for XI_FIXED
+  double omega;      // BGK relaxation
+  double c;          // diffusive weight of the WU set
+  double k;          // sigmoid sharpness; +inf selects the discontinuous split
+  int alpha_norm;    // 0: lambda_max of the sigmoid is the global max |lambda|
+                     //    (the CFL speed nu*xi); 1: max over the cell's own eigenvalues
+  int bc[2];         // per axis: BC_PERIODIC or BC_ZERO_GRADIENT
+  double T;          // end time (+inf: none)
+  int64_t max_steps; // step limit
+  double cluster_tol;// relative eigenvalue clustering tolerance
+  int threads;       // OpenMP threads (0: runtime default)
+} or_config;
+
+typedef struct {
+  double t;
+  int64_t steps;
+  double xi;          // streaming speed that the next step would use
+  double ch;          // cleaning speed that the next step would use (MHD)
+  int status;         // 0 ok, 1 non-physical state, 2 split failure
+  int64_t fail_step;
+  int64_t fail_cell;
+  double totals[PMAX];  // compensated (Neumaier) totals per field at the end
+  int threads_used;
+} or_result;
+
+}  // extern "C"
+
+namespace {
+
+int nvars(int kind, int dim) {
+  switch (kind) {
+    case SYS_SW: return dim + 1;
+    case SYS_EULER: return dim + 2;
+    case SYS_MHD: return 9;
+    case SYS_LINEAR: return 1;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Physical fluxes F^(d)(U). Templated so that the complex-step derivative can
+// be taken through the same expression.
+// ---------------------------------------------------------------------------
+template <class S>
+void flux(const or_config& cf, int d, const S* U, double ch, S* F) {
+  const int dim = cf.dim;
+  switch (cf.kind) {
+    case SYS_SW: {
+      // U = (h, h u_1, ..., h u_dim); F^(d) = (h u_d, h u_d u_k + g h^2/2 delta_kd)
+      S h = U[0];
+      S ud = U[1 + d] / h;
+      F[0] = U[1 + d];
+      for (int kk = 0; kk < dim; ++kk) F[1 + kk] = U[1 + kk] * ud;
+      F[1 + d] += 0.5 * cf.g * h * h;
+      break;
+    }
+    case SYS_EULER: {
+      // U = (rho, rho u, E); p = (gamma-1)(E - |rho u|^2/(2 rho))
+      S rho = U[0];
+      S E = U[dim + 1];
+      S m2 = 0.0;
+      for (int kk = 0; kk < dim; ++kk) m2 += U[1 + kk] * U[1 + kk];
+      S p = (cf.gamma - 1.0) * (E - 0.5 * m2 / rho);
+      S ud = U[1 + d] / rho;
+      F[0] = U[1 + d];
+      for (int kk = 0; kk < dim; ++kk) F[1 + kk] = U[1 + kk] * ud;
+      F[1 + d] += p;
+      F[dim + 1] = (E + p) * ud;
+      break;
+    }
+    case SYS_MHD: {
+      // U = (rho, rho u (3), E, B (3), psi); u and B are 3-vectors in 1D/2D.
+      S rho = U[0];
+      S u[3] = {U[1] / rho, U[2] / rho, U[3] / rho};
+      S E = U[4];
+      S B[3] = {U[5], U[6], U[7]};
+      S psi = U[8];
+      S uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+      S BB = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+      S uB = u[0] * B[0] + u[1] * B[1] + u[2] * B[2];
+      S p = (cf.gamma - 1.0) * (E - 0.5 * rho * uu - 0.5 * BB);
+      S pt = p + 0.5 * BB;
+      F[0] = rho * u[d];
+      for (int kk = 0; kk < 3; ++kk) F[1 + kk] = rho * u[d] * u[kk] - B[d] * B[kk];
+      F[1 + d] += pt;
+      F[4] = (E + pt) * u[d] - uB * B[d];
+      for (int kk = 0; kk < 3; ++kk) F[5 + kk] = u[d] * B[kk] - B[d] * u[kk];
+      F[5 + d] += psi;
+      F[8] = ch * ch * B[d];
+      break;
+    }
+    case SYS_LINEAR: {
+      F[0] = cf.adv[d] * U[0];
+      break;
+    }
+  }
+}
+
+// Fast magnetosonic speed in direction d (Sec. 5.3; mu_0 = 1 units).
+double mhd_cf(const or_config& cf, int d, const double* U) {
+  double rho = U[0];
+  double u[3] = {U[1] / rho, U[2] / rho, U[3] / rho};
+  double BB = U[5] * U[5] + U[6] * U[6] + U[7] * U[7];
+  double p = (cf.gamma - 1.0) * (U[4] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) - 0.5 * BB);
+  double a2 = cf.gamma * p / rho;
+  double b2 = BB / rho;
+  double bd2 = U[5 + d] * U[5 + d] / rho;
+  double s = a2 + b2;
+  double disc = std::sqrt(std::max(0.0, s * s - 4.0 * a2 * bd2));
+  return std::sqrt(0.5 * (s + disc));
+}
+
+// Closed-form eigenvalues of dF^(d)/dU, in ascending order.
+void eigenvalues(const or_config& cf, int d, const double* U, double ch, double* lam) {
+  const int dim = cf.dim;
+  switch (cf.kind) {
+    case SYS_SW: {
+      double h = U[0], ud = U[1 + d] / h, c = std::sqrt(cf.g * h);
+      if (dim == 1) { lam[0] = ud - c; lam[1] = ud + c; }
+      else { lam[0] = ud - c; lam[1] = ud; lam[2] = ud + c; }
+      break;
+    }
+    case SYS_EULER: {
+      double rho = U[0], E = U[dim + 1], m2 = 0.0;
+      for (int kk = 0; kk < dim; ++kk) m2 += U[1 + kk] * U[1 + kk];
+      double p = (cf.gamma - 1.0) * (E - 0.5 * m2 / rho);
+      double c = std::sqrt(cf.gamma * p / rho), ud = U[1 + d] / rho;
+      lam[0] = ud - c;
+      for (int kk = 0; kk < dim; ++kk) lam[1 + kk] = ud;
+      lam[dim + 1] = ud + c;
+      break;
+    }
+    case SYS_MHD: {
+      // u_d, u_d +- c_a, u_d +- c_s, u_d +- c_f and the cleaning pair +- c_h.
+      double rho = U[0];
+      double u[3] = {U[1] / rho, U[2] / rho, U[3] / rho};
+      double BB = U[5] * U[5] + U[6] * U[6] + U[7] * U[7];
+      double p = (cf.gamma - 1.0) * (U[4] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) - 0.5 * BB);
+      double a2 = cf.gamma * p / rho;
+      double bd2 = U[5 + d] * U[5 + d] / rho;
+      double bt2 = (BB - U[5 + d] * U[5 + d]) / rho;
+      // c_f^2 - c_s^2 written as a sum of squares, and c_s^2 from the product
+      // c_f^2 c_s^2 = a^2 b_d^2, so that neither root loses digits.
+      double disc = std::sqrt((a2 - bd2) * (a2 - bd2) + bt2 * (2.0 * a2 + 2.0 * bd2 + bt2));
+      double cf2 = 0.5 * (a2 + bd2 + bt2 + disc);
+      double cs2 = cf2 > 0.0 ? a2 * bd2 / cf2 : 0.0;
+      double cfv = std::sqrt(cf2), csv = std::sqrt(cs2), cav = std::sqrt(bd2);
+      double ud = u[d];
+      double v[9] = {ud - cfv, ud - cav, ud - csv, ud, ud + csv, ud + cav, ud + cfv, -ch, ch};
+      std::sort(v, v + 9);
+      for (int j = 0; j < 9; ++j) lam[j] = v[j];
+      break;
+    }
+    case SYS_LINEAR: lam[0] = cf.adv[d]; break;
+  }
+}
+
+// Complex-step Jacobian A[i][j] = dF_i/dU_j (row-major p x p).
+void jacobian(const or_config& cf, int d, const double* U, double ch, double* A) {
+  const int p = nvars(cf.kind, cf.dim);
+  const double hstep = 1e-30;
+  cd Uc[PMAX], Fc[PMAX];
+  for (int j = 0; j < p; ++j) {
+    for (int i = 0; i < p; ++i) Uc[i] = cd(U[i], 0.0);
+    Uc[j] = cd(U[j], hstep);
+    flux<cd>(cf, d, Uc, ch, Fc);
+    for (int i = 0; i < p; ++i) A[i * p + j] = Fc[i].imag() / hstep;
+  }
+}
+
+// Basis of the m-dimensional null space of the p x p matrix M, found by
+// Gaussian elimination with complete pivoting stopped after p - m pivots.
+// Vectors are returned with unit 2-norm in out[r*p + i].
+void nullspace(int p, double* M, int m, double* out) {
+  int col[PMAX];
+  for (int j = 0; j < p; ++j) col[j] = j;
+  const int rank = p - m;
+  for (int kk = 0; kk < rank; ++kk) {
+    int bi = kk, bj = kk;
+    double best = -1.0;
+    for (int i = kk; i < p; ++i)
+      for (int j = kk; j < p; ++j)
+        if (std::fabs(M[i * p + j]) > best) { best = std::fabs(M[i * p + j]); bi = i; bj = j; }
+    if (bi != kk)
+      for (int j = 0; j < p; ++j) std::swap(M[kk * p + j], M[bi * p + j]);
+    if (bj != kk) {
+      for (int i = 0; i < p; ++i) std::swap(M[i * p + kk], M[i * p + bj]);
+      std::swap(col[kk], col[bj]);
+    }
+    for (int i = kk + 1; i < p; ++i) {
+      double f = M[i * p + kk] / M[kk * p + kk];
+      for (int j = kk; j < p; ++j) M[i * p + j] -= f * M[kk * p + j];
+    }
+  }
+  for (int r = 0; r < m; ++r) {
+    double x[PMAX] = {0.0};
+    x[rank + r] = 1.0;
+    for (int kk = rank - 1; kk >= 0; --kk) {
+      double s = 0.0;
+      for (int j = kk + 1; j < p; ++j) s += M[kk * p + j] * x[j];
+      x[kk] = -s / M[kk * p + kk];
+    }
+    double nrm = 0.0;
+    for (int j = 0; j < p; ++j) nrm += x[j] * x[j];
+    nrm = std::sqrt(nrm);
+    for (int j = 0; j < p; ++j) out[r * p + col[j]] = x[j] / nrm;
+  }
+}
+
+// Solve P x = b (P is p x p, row-major) by LU with partial pivoting.
+bool lu_solve(int p, const double* Pin, const double* b, double* x) {
+  double P[PMAX * PMAX], y[PMAX];
+  std::memcpy(P, Pin, sizeof(double) * p * p);
+  std::memcpy(y, b, sizeof(double) * p);
+  for (int kk = 0; kk < p; ++kk) {
+    int bi = kk;
+    for (int i = kk + 1; i < p; ++i)
+      if (std::fabs(P[i * p + kk]) > std::fabs(P[bi * p + kk])) bi = i;
+    if (P[bi * p + kk] == 0.0) return false;
+    if (bi != kk) {
+      for (int j = 0; j < p; ++j) std::swap(P[kk * p + j], P[bi * p + j]);
+      std::swap(y[kk], y[bi]);
+    }
+    for (int i = kk + 1; i < p; ++i) {
+      double f = P[i * p + kk] / P[kk * p + kk];
+      for (int j = kk; j < p; ++j) P[i * p + j] -= f * P[kk * p + j];
+      y[i] -= f * y[kk];
+    }
+  }
+  for (int i = p - 1; i >= 0; --i) {
+    double s = y[i];
+    for (int j = i + 1; j < p; ++j) s -= P[i * p + j] * x[j];
+    x[i] = s / P[i * p + i];
+  }
+  return true;
+}
+
+// Sigmoid weight of Sec. 3.1: alpha = 1/(1 + exp(-k lambda / max_j|lambda_j|)).
+// k = +inf gives the discontinuous split of Sec. 2.2 (lambda >= 0 goes to +).
+double alpha_weight(double lam, double lmax, double k) {
+  if (std::isinf(k)) return lam >= 0.0 ? 1.0 : 0.0;
+  if (lmax == 0.0) return 0.5;
+  return 1.0 / (1.0 + std::exp(-k * lam / lmax));
+}
+
+// Weighted flux-vector split of F^(d)(U) (Sec. 2.2 expansion, Sec. 3.1 weights).
+// Lam is the global max |lambda| over cells, directions and eigenvalues of the
+// current state; it normalizes the sigmoid unless alpha_norm selects the
+// cell's own maximum. Returns false if the eigenvector matrix is singular.
+bool split(const or_config& cf, int d, const double* U, double ch, double Lam, double* Fp, double* Fm) {
+  const int p = nvars(cf.kind, cf.dim);
+  double F[PMAX], lam[PMAX], A[PMAX * PMAX];
+  flux<double>(cf, d, U, ch, F);
+  eigenvalues(cf, d, U, ch, lam);
+  jacobian(cf, d, U, ch, A);
+  double lmax = 0.0;
+  for (int j = 0; j < p; ++j) lmax = std::max(lmax, std::fabs(lam[j]));
+  const double lnorm = cf.alpha_norm == 0 ? Lam : lmax;
+  // Group (sorted) eigenvalues whose spacing is below cluster_tol * lmax;
+  // a cluster shares one weight and the joint null space is used.
+  double R[PMAX * PMAX];  // column j = right eigenvector r^j
+  double al[PMAX];
+  int j0 = 0;
+  while (j0 < p) {
+    int j1 = j0 + 1;
+    while (j1 < p && lam[j1] - lam[j1 - 1] <= cf.cluster_tol * lmax) ++j1;
+    const int m = j1 - j0;
+    double mean = 0.0;
+    for (int j = j0; j < j1; ++j) mean += lam[j];
+    mean /= m;
+    double M[PMAX * PMAX];
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < p; ++j) M[i * p + j] = A[i * p + j] - (i == j ? mean : 0.0);
+    double vecs[PMAX * PMAX];
+    nullspace(p, M, m, vecs);
+    for (int r = 0; r < m; ++r) {
+      for (int i = 0; i < p; ++i) R[i * p + (j0 + r)] = vecs[r * p + i];
+      al[j0 + r] = alpha_weight(mean, lnorm, cf.k);
+    }
+    j0 = j1;
+  }
+  double phi[PMAX];
+  if (!lu_solve(p, R, F, phi)) return false;
+  for (int i = 0; i < p; ++i) {
+    double sp = 0.0, sm = 0.0;
+    for (int j = 0; j < p; ++j) {
+      sp += al[j] * phi[j] * R[i * p + j];
+      sm += (1.0 - al[j]) * phi[j] * R[i * p + j];
+    }
+    Fp[i] = sp;
+    Fm[i] = sm;
+  }
+  for (int i = 0; i < p; ++i)
+    if (!std::isfinite(Fp[i]) || !std::isfinite(Fm[i])) return false;
+  return true;
+}
+
+// Weighted-upwind equilibrium set, populations ordered as the paper's
+// velocities: 1D (+xi, 0, -xi) (Sec. 3.1); 2D (+x, -x, 0, +y, -y) (Sec. 3.4).
+bool feq(const or_config& cf, const double* U, double xi, double ch, double Lam, double* out) {
+  const int p = nvars(cf.kind, cf.dim);
+  const double c = cf.c;
+  if (cf.dim == 1) {
+    double Fp[PMAX], Fm[PMAX];
+    if (!split(cf, 0, U, ch, Lam, Fp, Fm)) return false;
+    for (int i = 0; i < p; ++i) {
+      out[0 * p + i] = c * U[i] + Fp[i] / xi;
+      out[1 * p + i] = (1.0 - 2.0 * c) * U[i] - (Fp[i] - Fm[i]) / xi;
+      out[2 * p + i] = c * U[i] - Fm[i] / xi;
+    }
+  } else {
+    double F1p[PMAX], F1m[PMAX], F2p[PMAX], F2m[PMAX];
+    if (!split(cf, 0, U, ch, Lam, F1p, F1m)) return false;
+    if (!split(cf, 1, U, ch, Lam, F2p, F2m)) return false;
+    for (int i = 0; i < p; ++i) {
+      out[0 * p + i] = c * U[i] + F1p[i] / xi;
+      out[1 * p + i] = c * U[i] - F1m[i] / xi;
+      out[2 * p + i] = (1.0 - 4.0 * c) * U[i] - (F1p[i] + F2p[i] - F1m[i] - F2m[i]) / xi;
+      out[3 * p + i] = c * U[i] + F2p[i] / xi;
+      out[4 * p + i] = c * U[i] - F2m[i] / xi;
+    }
+  }
+  return true;
+}
+
+// Largest |eigenvalue| over directions at one state, and (MHD) the largest
+// fast speed; used for the CFL speed of Sec. 3.2 and for c_h = factor * c_f.
+void cell_speeds(const or_config& cf, const double* U, double ch, double* lam_abs, double* cf_max) {
+  const int p = nvars(cf.kind, cf.dim);
+  double lm = 0.0, cm = 0.0;
+  for (int d = 0; d < cf.dim; ++d) {
+    double lam[PMAX];
+    eigenvalues(cf, d, U, ch, lam);
+    for (int j = 0; j < p; ++j) lm = std::max(lm, std::fabs(lam[j]));
+    if (cf.kind == SYS_MHD) cm = std::max(cm, mhd_cf(cf, d, U));
+  }
+  *lam_abs = lm;
+  *cf_max = cm;
+}
+
+bool physical(const or_config& cf, const double* U) {
+  const int p = nvars(cf.kind, cf.dim);
+  for (int i = 0; i < p; ++i)
+    if (!std::isfinite(U[i])) return false;
+  switch (cf.kind) {
+    case SYS_SW: return U[0] > 0.0;
+    case SYS_EULER: {
+      double m2 = 0.0;
+      for (int kk = 0; kk < cf.dim; ++kk) m2 += U[1 + kk] * U[1 + kk];
+      double pr = (cf.gamma - 1.0) * (U[cf.dim + 1] - 0.5 * m2 / U[0]);
+      return U[0] > 0.0 && pr > 0.0;
+    }
+    case SYS_MHD: {
+      double rho = U[0];
+      double mm = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+      double BB = U[5] * U[5] + U[6] * U[6] + U[7] * U[7];
+      double pr = (cf.gamma - 1.0) * (U[4] - 0.5 * mm / rho - 0.5 * BB);
+      return rho > 0.0 && pr > 0.0;
+    }
+  }
+  return true;
+}
+
+// Source cell of the streamed population: index i - m along an axis of n
+// cells. Periodic wrap (Sec. 3.3, periodic boundary conditions). Zero
+// gradient: the ghost outside the domain carries the post-collision
+// populations of the adjacent boundary cell (a reading; the paper's own 1D
+// boundary is the characteristic one).
+int64_t src_index(int64_t i, int m, int64_t n, int bc) {
+  int64_t s = i - m;
+  if (s >= 0 && s < n) return s;
+  if (bc == BC_PERIODIC) return (s + n) % n;
+  return i;  // zero gradient: the boundary cell itself
+}
+
+// Neumaier compensated sum.
+double neumaier(const double* x, int64_t n) {
+  double s = 0.0, comp = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double t = s + x[i];
+    if (std::fabs(s) >= std::fabs(x[i])) comp += (s - t) + x[i];
+    else comp += (x[i] - t) + s;
+    s = t;
+  }
+  return s + comp;
+}
+
+struct Lattice {
+  int Q;
+  int mx[5], my[5];  // velocity components in units of xi
+};
+
+Lattice make_lattice(int dim) {
+  Lattice L{};
+  if (dim == 1) {
+    L.Q = 3;
+    int mx[3] = {1, 0, -1};
+    for (int q = 0; q < 3; ++q) { L.mx[q] = mx[q]; L.my[q] = 0; }
+  } else {
+    L.Q = 5;
+    int mx[5] = {1, -1, 0, 0, 0}, my[5] = {0, 0, 0, 1, -1};
+    for (int q = 0; q < 5; ++q) { L.mx[q] = mx[q]; L.my[q] = my[q]; }
+  }
+  return L;
+}
+
+struct Runner {
+  const or_config& cf;
+  int p, Q, dim;
+  int64_t nx, ny, N;
+  double dx;
+  Lattice L;
+  std::vector<double> f, fs, fn, U;  // f, f*, f^{n+1}: [q][var][cell]; U: [var][cell]
+
+  explicit Runner(const or_config& c) : cf(c) {
+    dim = cf.dim;
+    p = nvars(cf.kind, dim);
+    L = make_lattice(dim);
+    Q = L.Q;
+    nx = cf.n[0];
+    ny = dim == 2 ? cf.n[1] : 1;
+    N = nx * ny;
+    dx = (cf.hi[0] - cf.lo[0]) / double(nx);
+    f.assign(size_t(Q) * p * N, 0.0);
+    fs.assign(size_t(Q) * p * N, 0.0);
+    fn.assign(size_t(Q) * p * N, 0.0);
+    U.assign(size_t(p) * N, 0.0);
+  }
+  double& F(std::vector<double>& a, int q, int v, int64_t c) { return a[(size_t(q) * p + v) * N + c]; }
+
+  // U_i = sum_q f_{q,i}: first discrete moment (Sec. 2.1).
+  void moments() {
+    for (int v = 0; v < p; ++v)
+      for (int64_t c = 0; c < N; ++c) {
+        double s = 0.0;
+        for (int q = 0; q < Q; ++q) s += F(f, q, v, c);
+        U[size_t(v) * N + c] = s;
+      }
+  }
+
+  // Global max |lambda| and max c_f over the current moments.
+  void global_speeds(double ch, double* lam, double* cfm) {
+    double lm = 0.0, cm = 0.0;
+#pragma omp parallel for reduction(max : lm, cm) schedule(static)
+    for (int64_t c = 0; c < N; ++c) {
+      double Uc[PMAX];
+      for (int v = 0; v < p; ++v) Uc[v] = U[size_t(v) * N + c];
+      double a, b;
+      cell_speeds(cf, Uc, ch, &a, &b);
+      lm = std::max(lm, a);
+      cm = std::max(cm, b);
+    }
+    *lam = lm;
+    *cfm = cm;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int or_nvars(int kind, int dim) { return nvars(kind, dim); }
+
+void or_flux(const or_config* cf, int d, const double* U, double ch, double* F) { flux<double>(*cf, d, U, ch, F); }
+
+void or_eigenvalues(const or_config* cf, int d, const double* U, double ch, double* lam) {
+  eigenvalues(*cf, d, U, ch, lam);
+}
+
+void or_jacobian(const or_config* cf, int d, const double* U, double ch, double* A) { jacobian(*cf, d, U, ch, A); }
+
+int or_split(const or_config* cf, int d, const double* U, double ch, double Lam, double* Fp, double* Fm) {
+  return split(*cf, d, U, ch, Lam, Fp, Fm) ? 0 : 1;
+}
+
+int or_feq(const or_config* cf, const double* U, double xi, double ch, double Lam, double* out) {
+  return feq(*cf, U, xi, ch, Lam, out) ? 0 : 1;
+}
+
+// Global max |lambda| over the cells of U (SoA [var][cell]) and, for MHD, the
+// cleaning speed ch_factor * max c_f that goes with it.
+double or_global_lambda(const or_config* cfp, const double* U, int64_t ncell, double* ch_out) {
+  const or_config& cf = *cfp;
+  const int p = nvars(cf.kind, cf.dim);
+  double lm = 0.0, cm = 0.0;
+  for (int64_t c = 0; c < ncell; ++c) {
+    double Uc[PMAX], a, b;
+    for (int v = 0; v < p; ++v) Uc[v] = U[size_t(v) * ncell + c];
+    cell_speeds(cf, Uc, 0.0, &a, &b);
+    cm = std::max(cm, b);
+  }
+  double ch = cf.kind == SYS_MHD ? cf.ch_factor * cm : 0.0;
+  for (int64_t c = 0; c < ncell; ++c) {
+    double Uc[PMAX], a, b;
+    for (int v = 0; v < p; ++v) Uc[v] = U[size_t(v) * ncell + c];
+    cell_speeds(cf, Uc, ch, &a, &b);
+    lm = std::max(lm, a);
+  }
+  if (ch_out) *ch_out = ch;
+  return lm;
+}
+
+double or_fast_speed(const or_config* cf, int d, const double* U) { return mhd_cf(*cf, d, U); }
+
+// Full run following the flow chart of Sec. 3.5.
+//   U0:   initial conserved state, SoA [var][cell], cell = j*nx + i.
+//   Uout: final conserved state, same layout.
+//   fout: optional final populations [q][var][cell] (may be null).
+//   xi_hist: optional, receives xi^n for n = 0..min(steps, xi_cap)-1.
+int or_run(const or_config* cfp, const double* U0, double* Uout, double* fout, double* xi_hist, int64_t xi_cap,
+           or_result* res) {
+  const or_config& cf = *cfp;
+#ifdef _OPENMP
+  if (cf.threads > 0) omp_set_num_threads(cf.threads);
+  res->threads_used = omp_get_max_threads();
+#else
+  res->threads_used = 1;
+#endif
+  Runner R(cf);
+  const int p = R.p, Q = R.Q;
+  const int64_t N = R.N, nx = R.nx, ny = R.ny;
+  res->status = 0;
+  res->fail_step = -1;
+  res->fail_cell = -1;
+
+  // Initialization (Sec. 3.5): xi from the CFL rule with U(x,0); c_h from
+  // the fast speed of U(x,0); f_q(x,0) = f_q^eq(U(x,0)).
+  for (size_t i = 0; i < size_t(p) * N; ++i) R.U[i] = U0[i];
+  double ch = 0.0, lam = 0.0, cfm = 0.0;
+  R.global_speeds(0.0, &lam, &cfm);
+  if (cf.kind == SYS_MHD) {
+    ch = cf.ch_factor * cfm;
+    R.global_speeds(ch, &lam, &cfm);
+  }
+  double xi = cf.xi_mode == XI_CFL ? lam / cf.nu : cf.xi_fixed;
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int64_t c = 0; c < N; ++c) {
+    double Uc[PMAX], fe[5 * PMAX];
+    for (int v = 0; v < p; ++v) Uc[v] = R.U[size_t(v) * N + c];
+    if (!feq(cf, Uc, xi, ch, lam, fe)) { bad |= 1; continue; }
+    for (int q = 0; q < Q; ++q)
+      for (int v = 0; v < p; ++v) R.f[(size_t(q) * p + v) * N + c] = fe[q * p + v];
+  }
+  if (bad) { res->status = 2; res->fail_step = 0; }
+
+  double t = 0.0;
+  int64_t n = 0;
+  while (res->status == 0 && n < cf.max_steps && t < cf.T) {
+    // Time step update dt = dx/xi, landing on T (a reading: the last step
+    // lowers the CFL number so that t reaches T exactly).
+    double dt = R.dx / xi;
+    bool last = false;
+    if (std::isfinite(cf.T) && t + dt >= cf.T - 1e-9 * dt) {
+      xi = R.dx / (cf.T - t);
+      last = true;
+    }
+    if (xi_hist && n < xi_cap) xi_hist[n] = xi;
+    // lam holds Lambda^n = max |lambda(U^n)|, which normalizes the sigmoid.
+    // Moment recovery of the current populations (U^n = sum_q f_q^n).
+    R.moments();
+    // Collision (Sec. 3.5): f* = f - omega (f - f^eq(U^n)).
+    int sbad = 0;
+#pragma omp parallel for schedule(static) reduction(| : sbad)
+    for (int64_t c = 0; c < N; ++c) {
+      double Uc[PMAX], fe[5 * PMAX];
+      for (int v = 0; v < p; ++v) Uc[v] = R.U[size_t(v) * N + c];
+      if (!feq(cf, Uc, xi, ch, lam, fe)) { sbad |= 1; continue; }
+      for (int q = 0; q < Q; ++q)
+        for (int v = 0; v < p; ++v) {
+          size_t idx = (size_t(q) * p + v) * N + c;
+          R.fs[idx] = R.f[idx] - cf.omega * (R.f[idx] - fe[q * p + v]);
+        }
+    }
+    if (sbad) { res->status = 2; res->fail_step = n; break; }
+    // Streaming (Sec. 3.5): f_q(x + v_q dt, t + dt) = f*_q(x, t).
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        const int64_t c = j * nx + i;
+        for (int q = 0; q < Q; ++q) {
+          int64_t si = src_index(i, R.L.mx[q], nx, cf.bc[0]);
+          int64_t sj = R.dim == 2 ? src_index(j, R.L.my[q], ny, cf.bc[1]) : 0;
+          int64_t sc = sj * nx + si;
+          for (int v = 0; v < p; ++v)
+            R.fn[(size_t(q) * p + v) * N + c] = R.fs[(size_t(q) * p + v) * N + sc];
+        }
+      }
+    std::swap(R.f, R.fn);
+    t = last ? cf.T : t + dt;
+    n += 1;
+    // Moments of the new populations, admissibility check, CFL update of xi
+    // (and of c_h for MHD) from U^{n+1}.
+    R.moments();
+    int64_t fail = -1;
+    for (int64_t c = 0; c < N && fail < 0; ++c) {
+      double Uc[PMAX];
+      for (int v = 0; v < p; ++v) Uc[v] = R.U[size_t(v) * N + c];
+      if (!physical(cf, Uc)) fail = c;
+    }
+    if (fail >= 0) { res->status = 1; res->fail_step = n; res->fail_cell = fail; break; }
+    if (cf.kind == SYS_MHD) {
+      R.global_speeds(0.0, &lam, &cfm);
+      ch = cf.ch_factor * cfm;
+    }
+    R.global_speeds(ch, &lam, &cfm);
+    if (cf.xi_mode == XI_CFL) xi = lam / cf.nu;
+    else xi = cf.xi_fixed;
+  }
+  R.moments();
+  for (size_t i = 0; i < size_t(p) * N; ++i) Uout[i] = R.U[i];
+  if (fout) std::memcpy(fout, R.f.data(), sizeof(double) * R.f.size());
+  for (int v = 0; v < p; ++v) res->totals[v] = neumaier(&R.U[size_t(v) * N], N);
+  res->t = t;
+  res->steps = n;
+  res->xi = xi;
+  res->ch = ch;
+  return res->status;
+}
+
+}  // extern "C"
