@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Throughput of the WU-VKLB solver on one MI355X.
+
+One benchmark step = one full solve of the workload: initialization from an
+initial state already resident in HBM, then every time step to the end
+condition (collision, streaming, moments and the per-step CFL update, one
+fused HIP kernel per time step). Default workload: the 1D Euler shock tube,
+N = 65,536 cells to t = 0.2, FP32 (FP64 reported beside it).
+
+Prints one JSON line: value = cells x time steps / second (Mcell-steps/s) of
+the timed solves; roofline = algorithmic bytes of the step kernel (each
+population read once and written once, 2 Q p s bytes per cell-step) over its
+average launch duration, measured with HIP events on the solver's stream;
+cpu_baseline = the FP64 oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_2608_04283_amd import inputs as I  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (problem factory, precisions, cpu-baseline sample steps)
+    "euler1d_sod": (lambda: I.sod(65536), ("fp32", "fp64"), 1500),
+    "sw1d_dambreak": (lambda: I.dam_break(1000, c=0.5, k=0.0), ("fp64",), 600),
+    "euler2d_quadrants": (lambda: I.quadrants(2048, seed=0, steps=2000), ("fp32",), 4),
+    "mhd1d_briowu": (lambda: I.brio_wu(16384), ("fp32",), 300),
+    "mhd2d_orszag_tang": (lambda: I.orszag_tang(1024, steps=1000), ("fp32",), 2),
+}
+DEFAULT = "euler1d_sod"
+
+
+def alg_bytes_per_cell_step(P, prec):
+    return 2 * P.Q * P.p * (4 if prec == "fp32" else 8)
+
+
+def kernel_sources_sha():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2608_04283_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hpp", ".hip", ".inc")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload, prec, cells_per_launch):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{prec}.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel_sources_sha:\s*([0-9a-f]+)", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != kernel_sources_sha():
+        return None
+    return float(b.group(1))
+
+
+def time_workload(name, prec, K, W, quick=False):
+    import torch
+    from paper_2608_04283_amd import vklb
+
+    factory, _, _ = WORKLOADS[name]
+    P = factory()
+    s = vklb.Solver(P, precision=prec)
+    U0 = torch.from_numpy(P.U0).to("cuda").contiguous()
+    stream = torch.cuda.current_stream()
+    # warm-up solves; the first also fixes the number of time steps of a solve
+    steps = None
+    for _ in range(max(1, W)):
+        s.init_device(U0.data_ptr())
+        U, t, n = s.run()
+        steps = n
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    step_ms = 0.0
+    wall0 = time.perf_counter()
+    e0.record(stream)
+    for k in range(K):
+        s.init_device(U0.data_ptr())
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        s.step(steps)
+        b.record(stream)
+        if k == K - 1:
+            e1.record(stream)
+        torch.cuda.synchronize()
+        step_ms += a.elapsed_time(b)
+    e1.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = e0.elapsed_time(e1)
+    t_end, n_end, done = s.progress()
+    s.close()
+    assert n_end == steps and done, (n_end, steps, done)
+    cells = P.cells
+    cell_steps = cells * steps * K
+    value = cell_steps / (total_ms * 1e-3) / 1e6
+    launch_ms = step_ms / (steps * K)
+    achieved = alg_bytes_per_cell_step(P, prec) * cells / (launch_ms * 1e-3) / 1e9
+    traffic = profiled_traffic(name, prec, cells)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": f"k_step{P.dim}d", "avg_launch_us": round(launch_ms * 1e3, 3),
+            "alg_bytes_per_cell_step": alg_bytes_per_cell_step(P, prec), "cells_per_launch": cells}
+    return {"workload": P.name, "value": value, "ms_per_solve": total_ms / K, "steps_per_solve": steps,
+            "cells": cells, "t_end": t_end, "roofline": roof, "wall_s": wall, "dtype": "f32" if prec == "fp32" else "f64"}
+
+
+def cpu_baseline(name):
+    from oracle import oracle as O
+    factory, _, sample_steps = WORKLOADS[name]
+    P = factory()
+    kw = dict(system=P.system, dim=P.dim, n=P.n if P.dim == 2 else (P.n[0], 1), lo=P.lo, hi=P.hi, g=P.g,
+              gamma=P.gamma, ch_factor=P.ch_factor, adv=P.adv, xi_mode=P.xi_mode, nu=P.nu, xi=P.xi,
+              omega=P.omega, c=P.c, k=P.k, bc=P.bc, T=P.T, max_steps=sample_steps)
+    cf = O.make_config(**kw)
+    t0 = time.perf_counter()
+    r = O.run(cf, P.U0)
+    dt = time.perf_counter() - t0
+    return {"value": round(P.cells * r["steps"] / dt / 1e6, 3), "unit": "Mcell-steps/s", "cores": r["threads"],
+            "kind": "oracle",
+            "sample": f"first {r['steps']} time steps of {P.name} (FP64 oracle, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed full solves")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-also", action="store_true", help="skip the other workloads")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the solver runs on a single MI355X (no multi-GPU path)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    _, precs, _ = WORKLOADS[args.workload]
+    prec = args.precision or precs[0]
+    main_res = time_workload(args.workload, prec, args.steps, args.warmup)
+    out = {
+        "metric": "Mcell-steps/s",
+        "value": round(main_res["value"], 2),
+        "unit": "Mcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_solve"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": main_res["dtype"],
+        "data": "synthetic",
+        "config": {"workload": main_res["workload"], "cells": main_res["cells"],
+                   "time_steps_per_solve": main_res["steps_per_solve"], "t_end": main_res["t_end"],
+                   "lattice": "D1Q3" if "1d" in args.workload else "D2Q5", "omega": 1.0, "c": 0.05, "k": 2.0},
+        "roofline": main_res["roofline"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    extra = {}
+    for p2 in precs:
+        if p2 != prec:
+            r = time_workload(args.workload, p2, max(1, args.steps // 2), 1)
+            extra[p2] = {"value": round(r["value"], 2), "ms_per_solve": round(r["ms_per_solve"], 4),
+                         "roofline": r["roofline"]}
+    if extra:
+        out["other_precision"] = extra
+    if not args.no_also:
+        also = {}
+        for name, (_, wprecs, _) in WORKLOADS.items():
+            if name == args.workload:
+                continue
+            r = time_workload(name, wprecs[0], 2, 1)
+            also[name] = {"value": round(r["value"], 2), "dtype": r["dtype"], "ms_per_solve": round(r["ms_per_solve"], 3),
+                          "steps_per_solve": r["steps_per_solve"], "roofline": r["roofline"]}
+        out["also"] = also
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * vklb.h -- C ABI of the MI355X (gfx950) weighted-upwind vector kinetic
+ * lattice Boltzmann (WU-VKLB) solver.
+ *
+ * The method (Brown, Chaudhry, Shadid): vector populations f_q(x) in R^p
+ * stream along lattice velocities v_q and relax to a weighted-upwind
+ * equilibrium built from the conserved moments U = sum_q f_q and a
+ * sigmoid-weighted eigen-split of the physical flux.
+ *
+ * Conventions used by every entry point
+ *   - Every call returns vklb_status (VKLB_OK = 0). No exception or abort
+ *     crosses the ABI; a failing call leaves a message for vklb_last_error().
+ *   - Host arrays of conserved variables are FP64, structure of arrays:
+ *     U[var * cells + cell], cell = j * n[0] + i (x fastest).
+ *   - Variable order: shallow water (h, h u, [h v]); Euler (rho, rho u,
+ *     [rho v], E); MHD-GLM (rho, rho u, rho v, rho w, E, B_x, B_y, B_z, psi)
+ *     with three-component u and B in 1D and 2D; linear test system (u).
+ *   - Population order: D1Q3 (+xi, 0, -xi); D2Q5 (+x, -x, 0, +y, -y).
+ *   - Ownership: the caller owns host arrays, the device buffer passed to
+ *     vklb_create (or the library allocates one when none is passed) and the
+ *     HIP stream. The library owns the solver handle only.
+ *   - Asynchrony: vklb_init, vklb_step and vklb_set_state enqueue work on
+ *     the solver's stream and return; vklb_moments, vklb_diagnostics and
+ *     vklb_get_state synchronize the stream and report device-side errors
+ *     (non-physical states) detected since the last synchronizing call.
+ */
+#ifndef VKLB_H
+#define VKLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VKLB_OK = 0,
+  VKLB_ERR_ARG = -1,          /* invalid argument (see vklb_last_error) */
+  VKLB_ERR_UNSUPPORTED = -2,  /* combination not built (e.g. lattice/grid mismatch) */
+  VKLB_ERR_OOM = -3,          /* device buffer too small or allocation failed */
+  VKLB_ERR_DEVICE = -4,       /* a HIP runtime call failed */
+  VKLB_ERR_NONPHYSICAL = -5,  /* h, rho or p <= 0, or a non-finite value, was produced */
+  VKLB_ERR_STATE = -6         /* call out of order (e.g. vklb_step before vklb_init) */
+} vklb_status;
+
+/* Hyperbolic systems (Sec. 5.1 shallow water, 5.2 Euler, 5.3 ideal MHD with
+ * hyperbolic divergence cleaning; the linear system F^(d) = adv[d] u is a
+ * test system with an exact Fourier solution). */
+typedef enum { VKLB_SHALLOW_WATER = 0, VKLB_EULER = 1, VKLB_MHD_GLM = 2, VKLB_LINEAR = 3 } vklb_system_kind;
+
+typedef struct {
+  vklb_system_kind kind;
+  double g;          /* gravity (shallow water) */
+  double gamma;      /* adiabatic index (Euler, MHD) */
+  double ch_factor;  /* MHD cleaning speed c_h = ch_factor * max c_f over the grid (6 in Sec. 5.3) */
+  double adv[2];     /* advection speeds of the linear test system */
+} vklb_system;
+
+/* Lattices of Sec. 2.2 (D1Q3) and Sec. 3.4 (D2Q5); both include the rest velocity. */
+typedef enum { VKLB_D1Q3 = 0, VKLB_D2Q5 = 1 } vklb_lattice;
+
+/* Uniform cell-centred grid (Sec. 3.3: nodes dx/2 from the boundary). In 2D
+ * the lattice needs dx == dy (Sec. 3.4). */
+typedef struct {
+  int dim;          /* 1 or 2; must match the lattice */
+  int64_t n[2];     /* cells per axis; n[1] ignored in 1D */
+  double lo[2], hi[2];
+} vklb_grid;
+
+/* Streaming speed xi = dx/dt (the "lambda" of the interface). CFL mode
+ * updates it every step as max|lambda(U^n)| / nu (Sec. 3.2, 0 < nu <= 1);
+ * FIXED keeps xi constant. With an end time, the step that reaches it uses
+ * xi = dx / (T - t) so that t lands on T. */
+typedef enum { VKLB_XI_CFL = 0, VKLB_XI_FIXED = 1 } vklb_xi_mode;
+typedef struct {
+  vklb_xi_mode mode;
+  double nu;  /* CFL number (CFL mode) */
+  double xi;  /* streaming speed (FIXED mode) */
+} vklb_speed;
+
+/* Boundary per axis: periodic (Sec. 3.3) or zero gradient (the ghost beyond a
+ * boundary carries the post-collision populations of the boundary cell). */
+typedef enum { VKLB_BC_PERIODIC = 0, VKLB_BC_ZERO_GRADIENT = 1 } vklb_bc;
+
+/* Weighted-upwind equilibrium (Sec. 3.1, Sec. 3.4): diffusive weight c and
+ * sigmoid sharpness k (k = INFINITY selects the discontinuous split of
+ * Sec. 2.2; c = 1/3 (1D) or 1/5 (2D) with k = 0 gives the centered set).
+ * The sigmoid normalizer max_j|lambda_j| is the global max over the grid
+ * (alpha_local = 0) or the cell's own max for that direction (1). */
+typedef struct {
+  double c;
+  double k;
+  int alpha_local;
+} vklb_equilibrium;
+
+/* Storage/arithmetic precision of the populations. FP32 keeps FP64 for the
+ * MHD eigen-split, the time t, the streaming speed and the diagnostics. */
+typedef enum { VKLB_FP64 = 0, VKLB_FP32 = 1 } vklb_precision;
+
+typedef struct {
+  int basis;        /* 0: default (FP64 -> populations, FP32 -> moving populations + U);
+                       1: all Q populations; 2: moving populations + U in the rest slot */
+  int band_rows;    /* 2D: rows per workgroup band (8..64); 0 = tuned default */
+  int graph_chunk;  /* steps captured per HIP graph (0 = 64; < 0: plain launches) */
+  int strip_width;  /* 2D: columns per workgroup (64, 128 or 256); 0 = tuned default */
+} vklb_options;
+
+typedef struct vklb_solver vklb_solver;
+
+typedef struct {
+  double t;            /* current time */
+  int64_t steps;       /* steps taken since vklb_init / vklb_set_state */
+  double xi;           /* streaming speed the next step will use */
+  double lambda_max;   /* global max |lambda| of the current state */
+  double ch;           /* MHD cleaning speed of the current state (0 otherwise) */
+  int done;            /* end time or step limit reached */
+  int nonphysical;     /* 1 if a non-physical state was produced */
+  int64_t fail_step;   /* step that produced it (-1 if none) */
+  int64_t fail_cell;   /* lowest cell index where it was seen (-1 if none) */
+  double totals[9];    /* compensated (Neumaier) sum of each conserved field over the cells */
+  double max_div_b;    /* MHD 2D: max |dBx/dx + dBy/dy| by central differences; 0 otherwise */
+} vklb_diag;
+
+/* Bytes of device memory a solve needs (state, FP64 staging of U, two
+ * population buffers, reduction partials). 0 if the arguments are invalid. */
+size_t vklb_workspace_bytes(const vklb_system* sys, vklb_lattice lat, const vklb_grid* grid, vklb_precision prec);
+
+/* Create a solver. device_buf (>= vklb_workspace_bytes, 256-byte aligned) may be
+ * NULL, in which case the library allocates it with hipMalloc and frees it in
+ * vklb_destroy. hip_stream (a hipStream_t) may be NULL for the null stream.
+ * opt may be NULL for defaults. Checks: 0 < omega <= 2 (Sec. 2.3), 0 < nu <= 1
+ * (Sec. 3.2), c >= 0, k >= 0, dx == dy in 2D, lattice dimension == grid
+ * dimension; c > (1 - nu)/2 (Sec. 4.2) is accepted with a note in
+ * vklb_last_error. */
+vklb_status vklb_create(const vklb_system* sys, vklb_lattice lat, const vklb_grid* grid, const vklb_speed* lambda,
+                        double omega, const vklb_bc bc[2], const vklb_equilibrium* eq, vklb_precision prec,
+                        const vklb_options* opt, void* device_buf, size_t buf_bytes, void* hip_stream,
+                        vklb_solver** out);
+
+/* Set the end condition: steps past time T (T = INFINITY: none) or past
+ * max_steps (< 0: none) become no-ops. Call before vklb_init. */
+vklb_status vklb_set_end(vklb_solver* s, double T, int64_t max_steps);
+
+/* Initialization (Sec. 3.5): xi^0 and c_h^0 from U0, f_q = f_q^eq(U0), t = 0.
+ * U0_host: FP64 SoA [p][cells] in host memory (copied before return). */
+vklb_status vklb_init(vklb_solver* s, const double* U0_host);
+
+/* As vklb_init, with U0 already in device memory (FP64 SoA [p][cells]); the
+ * copy and the initialization are enqueued on the solver's stream. */
+vklb_status vklb_init_device(vklb_solver* s, const double* U0_device);
+
+/* Advance n steps on the solver's stream (collision, streaming, moments and
+ * the CFL update of Sec. 3.5, one fused kernel per step). No host sync. */
+vklb_status vklb_step(vklb_solver* s, int64_t n);
+
+/* Copy U = sum_q f_q to U_host (FP64 SoA [p][cells]); t and steps may be NULL.
+ * Synchronizes; returns VKLB_ERR_NONPHYSICAL if such a state was produced. */
+vklb_status vklb_moments(vklb_solver* s, double* U_host, double* t, int64_t* steps);
+
+/* Time, step count and whether the end condition has been reached (no more
+ * steps will run). Synchronizes; reports non-physical states like vklb_moments. */
+vklb_status vklb_progress(vklb_solver* s, double* t, int64_t* steps, int* done);
+
+/* Scalars and compensated totals of the current state. Synchronizes. */
+vklb_status vklb_diagnostics(vklb_solver* s, vklb_diag* d);
+
+/* Checkpoint / resume. The blob (vklb_state_bytes bytes) holds the stored
+ * population planes ([q][var][cell], the solver's precision and basis)
+ * followed by a 128-byte trailer with t, the step count, xi, Lambda, c_h, the
+ * end-time landing flag and the solve's shape. vklb_set_state restores all of
+ * it, so a resumed run continues bit for bit; it rejects (VKLB_ERR_ARG) a blob
+ * written by a solver of another system, lattice, size, precision or basis. */
+size_t vklb_state_bytes(const vklb_solver* s);
+vklb_status vklb_get_state(vklb_solver* s, void* host, double* t, int64_t* steps);
+vklb_status vklb_set_state(vklb_solver* s, const void* host);
+
+/* Time of the last vklb_step call's kernels, from HIP events on the solver's
+ * stream (ms; synchronizes). */
+vklb_status vklb_last_step_ms(vklb_solver* s, double* ms);
+
+void vklb_destroy(vklb_solver* s);
+const char* vklb_status_str(vklb_status st);
+const char* vklb_last_error(const vklb_solver* s); /* s may be NULL: last create error */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VKLB_H */

@@ -1,0 +1,441 @@
+// Per-cell arithmetic of the weighted-upwind vector kinetic lattice Boltzmann
+// step: physical fluxes, characteristic speeds, the sigmoid-weighted flux
+// split and the weighted-upwind equilibrium. Host+device functions; the GPU
+// kernels and the host-side cell check both include this header.
+//
+// The split is written as F+ = F/2 + D and F- = F/2 - D with
+//   D = sum_j beta(lambda_j) phi_j r_j,  beta = alpha - 1/2 = tanh(k lambda / (2 Lambda)) / 2,
+// which is the weighted splitting of Sec. 3.1 (alpha = 1/(1+exp(-k lambda/Lambda)))
+// rearranged; D is evaluated per system in closed form, without forming
+// the eigenvector matrix P or solving P Phi = F:
+//   * linear advection: one wave;
+//   * shallow water (Sec. 5.1): the two acoustic waves (the shear wave of the
+//     2D system carries no flux);
+//   * Euler (Sec. 5.2): the flux is homogeneous of degree one, so
+//     D = P diag(beta_j lambda_j) P^-1 U, the Steger-Warming formula with each
+//     eigenvalue scaled by its weight;
+//   * ideal MHD with divergence cleaning (Sec. 5.3): the Jacobian is block
+//     triangular, [[A7, C], [0, G]] with the (B_n, psi) pair in G. D on the
+//     seven-wave block uses Roe-Balsara normalized primitive eigenvectors
+//     (well defined at coinciding speeds); the coupling through C uses divided
+//     differences of beta between each seven-wave speed and +-c_h; on the
+//     cleaning pair D = beta(c_h) c_h (B_n, psi).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace vklb {
+
+enum Kind { K_SW = 0, K_EULER = 1, K_MHD = 2, K_LINEAR = 3 };
+
+// Physical and method parameters of one solve (read-only in kernels).
+struct Phys {
+  double g, gamma, ch_factor;
+  double adv[2];
+  double omega, c, k;
+  int kinf;         // 1: discontinuous split (k = infinity)
+  int alpha_local;  // 1: normalize the sigmoid by the cell's own max |lambda|
+};
+
+template <int KIND, int DIM>
+struct SysInfo;
+template <> struct SysInfo<K_SW, 1> { static constexpr int P = 2; };
+template <> struct SysInfo<K_SW, 2> { static constexpr int P = 3; };
+template <> struct SysInfo<K_EULER, 1> { static constexpr int P = 3; };
+template <> struct SysInfo<K_EULER, 2> { static constexpr int P = 4; };
+template <> struct SysInfo<K_MHD, 1> { static constexpr int P = 9; };
+template <> struct SysInfo<K_MHD, 2> { static constexpr int P = 9; };
+template <> struct SysInfo<K_LINEAR, 1> { static constexpr int P = 1; };
+template <> struct SysInfo<K_LINEAR, 2> { static constexpr int P = 1; };
+
+template <class S>
+__host__ __device__ inline S sq(S a) { return a * a; }
+
+// beta(lambda) = alpha(lambda) - 1/2 for the sigmoid of Sec. 3.1.
+template <class S>
+__host__ __device__ inline S beta_w(S lam, S half_k_over_L, int kinf) {
+  if (kinf) return lam >= S(0) ? S(0.5) : S(-0.5);
+  return S(0.5) * tanh(lam * half_k_over_L);
+}
+
+// Divided difference (beta(a) - beta(b)) / (a - b), with the derivative when
+// the two speeds (nearly) coincide.
+template <class S>
+__host__ __device__ inline S beta_dd(S a, S b, S half_k_over_L, int kinf) {
+  S d = a - b;
+  S ba = beta_w(a, half_k_over_L, kinf), bb = beta_w(b, half_k_over_L, kinf);
+  const S rel = sizeof(S) == 4 ? S(1e-3) : S(1e-6);
+  if (fabs(d) > rel * (fabs(a) + fabs(b)) || kinf) return d != S(0) ? (ba - bb) / d : S(0);
+  S tm = tanh(S(0.5) * (a + b) * half_k_over_L);
+  return S(0.5) * half_k_over_L * (S(1) - tm * tm);
+}
+
+// ---------------------------------------------------------------------------
+// Cell speeds: max |lambda| over directions and (MHD) the max fast speed.
+// ---------------------------------------------------------------------------
+template <int KIND, int DIM, class S>
+struct Cell;
+
+// ----------------------------- linear advection ----------------------------
+template <int DIM, class S>
+struct Cell<K_LINEAR, DIM, S> {
+  static constexpr int P = 1;
+  __host__ __device__ static void speeds(const S* U, const Phys& ph, S* lam, S* cfm) {
+    S m = S(0);
+    for (int d = 0; d < DIM; ++d) m = fmax(m, fabs(S(ph.adv[d])));
+    *lam = m;
+    *cfm = S(0);
+  }
+  __host__ __device__ static bool admissible(const S* U, const Phys&) { return isfinite(U[0]); }
+  // F^(d) and D^(d); Lam normalizes the sigmoid (global max |lambda|), ch unused.
+  __host__ __device__ static void split(int d, const S* U, const Phys& ph, S Lam, S, S* F, S* D) {
+    S a = S(ph.adv[d]);
+    S L = ph.alpha_local ? fabs(a) : Lam;
+    S hk = L > S(0) ? S(0.5 * ph.k) / L : S(0);
+    F[0] = a * U[0];
+    D[0] = beta_w(a, hk, ph.kinf) * a * U[0];
+  }
+};
+
+// ------------------------------- shallow water -----------------------------
+template <int DIM, class S>
+struct Cell<K_SW, DIM, S> {
+  static constexpr int P = DIM + 1;
+  __host__ __device__ static void speeds(const S* U, const Phys& ph, S* lam, S* cfm) {
+    S h = U[0];
+    S c = sqrt(S(ph.g) * h);
+    S m = S(0);
+    for (int d = 0; d < DIM; ++d) m = fmax(m, fabs(U[1 + d] / h) + c);
+    *lam = m;
+    *cfm = S(0);
+  }
+  __host__ __device__ static bool admissible(const S* U, const Phys&) {
+    bool ok = U[0] > S(0);
+    for (int i = 0; i < P; ++i) ok = ok && isfinite(U[i]);
+    return ok;
+  }
+  __host__ __device__ static void split(int d, const S* U, const Phys& ph, S Lam, S, S* F, S* D) {
+    const S h = U[0];
+    const S g = S(ph.g);
+    const S ud = U[1 + d] / h;
+    const S c = sqrt(g * h);
+    F[0] = U[1 + d];
+    for (int kk = 0; kk < DIM; ++kk) F[1 + kk] = U[1 + kk] * ud;
+    F[1 + d] += S(0.5) * g * h * h;
+    const S lm = ud - c, lp = ud + c;
+    const S L = ph.alpha_local ? fmax(fabs(lm), fabs(lp)) : Lam;
+    const S hk = L > S(0) ? S(0.5 * ph.k) / L : S(0);
+    // coefficients of the two acoustic waves: phi = h (2 u_d -+ c) / 4
+    const S wm = beta_w(lm, hk, ph.kinf) * h * (S(2) * ud - c) * S(0.25);
+    const S wp = beta_w(lp, hk, ph.kinf) * h * (S(2) * ud + c) * S(0.25);
+    D[0] = wm + wp;
+    for (int kk = 0; kk < DIM; ++kk) D[1 + kk] = (U[1 + kk] / h) * (wm + wp);
+    D[1 + d] = lm * wm + lp * wp;
+  }
+};
+
+// ----------------------------------- Euler ---------------------------------
+template <int DIM, class S>
+struct Cell<K_EULER, DIM, S> {
+  static constexpr int P = DIM + 2;
+  __host__ __device__ static S pressure(const S* U, S gamma) {
+    S m2 = S(0);
+    for (int kk = 0; kk < DIM; ++kk) m2 += U[1 + kk] * U[1 + kk];
+    return (gamma - S(1)) * (U[DIM + 1] - S(0.5) * m2 / U[0]);
+  }
+  __host__ __device__ static void speeds(const S* U, const Phys& ph, S* lam, S* cfm) {
+    const S gamma = S(ph.gamma);
+    const S rho = U[0];
+    const S c = sqrt(gamma * pressure(U, gamma) / rho);
+    S m = S(0);
+    for (int d = 0; d < DIM; ++d) m = fmax(m, fabs(U[1 + d] / rho) + c);
+    *lam = m;
+    *cfm = S(0);
+  }
+  __host__ __device__ static bool admissible(const S* U, const Phys& ph) {
+    bool ok = U[0] > S(0) && pressure(U, S(ph.gamma)) > S(0);
+    for (int i = 0; i < P; ++i) ok = ok && isfinite(U[i]);
+    return ok;
+  }
+  __host__ __device__ static void split(int d, const S* U, const Phys& ph, S Lam, S, S* F, S* D) {
+    const S gamma = S(ph.gamma);
+    const S rho = U[0];
+    const S irho = S(1) / rho;
+    S vel[DIM];
+    S v2 = S(0);
+    for (int kk = 0; kk < DIM; ++kk) { vel[kk] = U[1 + kk] * irho; v2 += vel[kk] * vel[kk]; }
+    const S E = U[DIM + 1];
+    const S p = (gamma - S(1)) * (E - S(0.5) * rho * v2);
+    const S c = sqrt(gamma * p * irho);
+    const S ud = vel[d];
+    F[0] = U[1 + d];
+    for (int kk = 0; kk < DIM; ++kk) F[1 + kk] = U[1 + kk] * ud;
+    F[1 + d] += p;
+    F[DIM + 1] = (E + p) * ud;
+    const S l1 = ud - c, l3 = ud + c;
+    const S L = ph.alpha_local ? fmax(fabs(l1), fabs(l3)) : Lam;
+    const S hk = L > S(0) ? S(0.5 * ph.k) / L : S(0);
+    const S mu1 = beta_w(l1, hk, ph.kinf) * l1;
+    const S mu2 = beta_w(ud, hk, ph.kinf) * ud;
+    const S mu3 = beta_w(l3, hk, ph.kinf) * l3;
+    const S H = (E + p) * irho;
+    const S s = rho / (S(2) * gamma);
+    const S ent = S(2) * (gamma - S(1)) * mu2;
+    D[0] = s * (ent + mu1 + mu3);
+    for (int kk = 0; kk < DIM; ++kk) D[1 + kk] = s * (ent + mu1 + mu3) * vel[kk];
+    D[1 + d] += s * c * (mu3 - mu1);
+    D[DIM + 1] = s * (ent * S(0.5) * v2 + mu1 * (H - ud * c) + mu3 * (H + ud * c));
+  }
+};
+
+// ------------------------- ideal MHD with GLM cleaning ----------------------
+// Conserved order: rho, m_x, m_y, m_z, E, B_x, B_y, B_z, psi (3-vectors in 1D/2D).
+template <int DIM, class S>
+struct Cell<K_MHD, DIM, S> {
+  static constexpr int P = 9;
+
+  __host__ __device__ static S pressure(const S* U, S gamma) {
+    S m2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+    S B2 = U[5] * U[5] + U[6] * U[6] + U[7] * U[7];
+    return (gamma - S(1)) * (U[4] - S(0.5) * m2 / U[0] - S(0.5) * B2);
+  }
+  // fast speed along direction d
+  __host__ __device__ static S fast(const S* U, S gamma, int d) {
+    const S rho = U[0];
+    const S a2 = gamma * pressure(U, gamma) / rho;
+    const S bn2 = U[5 + d] * U[5 + d] / rho;
+    const S bt2 = (U[5] * U[5] + U[6] * U[6] + U[7] * U[7]) / rho - bn2;
+    const S disc = sqrt(sq(a2 - bn2) + bt2 * (S(2) * a2 + S(2) * bn2 + bt2));
+    return sqrt(S(0.5) * (a2 + bn2 + bt2 + disc));
+  }
+  __host__ __device__ static void speeds(const S* U, const Phys& ph, S* lam, S* cfm) {
+    const S gamma = S(ph.gamma);
+    S m = S(0), cm = S(0);
+    for (int d = 0; d < DIM; ++d) {
+      const S cf = fast(U, gamma, d);
+      m = fmax(m, fabs(U[1 + d] / U[0]) + cf);
+      cm = fmax(cm, cf);
+    }
+    *lam = m;   // seven-wave max; the cleaning speed joins it globally
+    *cfm = cm;
+  }
+  __host__ __device__ static bool admissible(const S* U, const Phys& ph) {
+    bool ok = U[0] > S(0) && pressure(U, S(ph.gamma)) > S(0);
+    for (int i = 0; i < P; ++i) ok = ok && isfinite(U[i]);
+    return ok;
+  }
+
+  // Primitive-variable wave decomposition along the normal direction.
+  struct Waves {
+    S rho, sr, a, a2, cf, cs, af, as, by, bz, sgn;
+  };
+
+  // Coefficients (f-, a-, s-, e, s+, a+, f+) of a primitive 7-vector
+  // x = (rho, u_n, u_t1, u_t2, p, B_t1, B_t2) in the right eigenvectors.
+  __host__ __device__ static void project(const Waves& w, const S* x, S* c) {
+    const S xvp = w.by * x[2] + w.bz * x[3];
+    const S xvq = -w.bz * x[2] + w.by * x[3];
+    const S xbp = w.by * x[5] + w.bz * x[6];
+    const S xbq = -w.bz * x[5] + w.by * x[6];
+    const S X = x[4] / (w.rho * w.a2);
+    const S Y = xbp / (w.a * w.sr);
+    const S Fp = w.af * X + w.as * Y;
+    const S Sp = w.as * X - w.af * Y;
+    const S Z1 = x[1], Z2 = w.sgn * xvp;
+    const S ia2 = S(1) / w.a2;
+    const S Fm = (w.af * w.cf * Z1 - w.as * w.cs * Z2) * ia2;
+    const S Sm = (w.as * w.cs * Z1 + w.af * w.cf * Z2) * ia2;
+    const S Ap = xbq / w.sr, Am = -w.sgn * xvq;
+    c[0] = S(0.5) * (Fp - Fm);
+    c[6] = S(0.5) * (Fp + Fm);
+    c[2] = S(0.5) * (Sp - Sm);
+    c[4] = S(0.5) * (Sp + Sm);
+    c[1] = S(0.5) * (Ap - Am);
+    c[5] = S(0.5) * (Ap + Am);
+    c[3] = x[0] - x[4] * ia2;
+  }
+  // sum_j c_j r_j (primitive 7-vector) for the same eigenvectors.
+  __host__ __device__ static void combine(const Waves& w, const S* c, S* y) {
+    const S Fp = c[6] + c[0], Fm = c[6] - c[0];
+    const S Sp = c[4] + c[2], Sm = c[4] - c[2];
+    const S Ap = c[5] + c[1], Am = c[5] - c[1];
+    const S pf = w.af * Fp + w.as * Sp;
+    y[0] = c[3] + w.rho * pf;
+    y[1] = w.af * w.cf * Fm + w.as * w.cs * Sm;
+    const S vp = w.sgn * (-w.as * w.cs * Fm + w.af * w.cf * Sm);
+    const S vq = -w.sgn * Am;
+    y[2] = w.by * vp - w.bz * vq;
+    y[3] = w.bz * vp + w.by * vq;
+    y[4] = w.rho * w.a2 * pf;
+    const S bp = w.a * w.sr * (w.as * Fp - w.af * Sp);
+    const S bq = w.sr * Ap;
+    y[5] = w.by * bp - w.bz * bq;
+    y[6] = w.bz * bp + w.by * bq;
+  }
+
+  __host__ __device__ static void split(int d, const S* Ug, const Phys& ph, S Lam, S ch, S* Fg, S* Dg) {
+    const S gamma = S(ph.gamma);
+    const S gm1 = gamma - S(1);
+    // local frame: n = d, t1 = the other in-plane axis, t2 = z
+    const int n = d, t1 = 1 - d, t2 = 2;
+    const S rho = Ug[0];
+    const S irho = S(1) / rho;
+    const S u = Ug[1 + n] * irho, v = Ug[1 + t1] * irho, w = Ug[1 + t2] * irho;
+    const S E = Ug[4];
+    const S Bn = Ug[5 + n], By = Ug[5 + t1], Bz = Ug[5 + t2];
+    const S psi = Ug[8];
+    const S uu = u * u + v * v + w * w;
+    const S BB = Bn * Bn + By * By + Bz * Bz;
+    const S uB = u * Bn + v * By + w * Bz;
+    const S p = gm1 * (E - S(0.5) * rho * uu - S(0.5) * BB);
+    const S pt = p + S(0.5) * BB;
+    // flux in the local frame
+    S F[9];
+    F[0] = rho * u;
+    F[1] = rho * u * u + pt - Bn * Bn;
+    F[2] = rho * u * v - Bn * By;
+    F[3] = rho * u * w - Bn * Bz;
+    F[4] = (E + pt) * u - uB * Bn;
+    F[5] = psi;
+    F[6] = u * By - Bn * v;
+    F[7] = u * Bz - Bn * w;
+    F[8] = ch * ch * Bn;
+    // wave speeds and Roe-Balsara normalization
+    Waves W;
+    W.rho = rho;
+    W.sr = sqrt(rho);
+    W.a2 = gamma * p * irho;
+    W.a = sqrt(W.a2);
+    const S bn2 = Bn * Bn * irho;
+    const S bt2r = By * By + Bz * Bz;
+    const S bt2 = bt2r * irho;
+    const S b2 = bn2 + bt2;
+    const S disc = sqrt(sq(W.a2 - bn2) + bt2 * (S(2) * W.a2 + S(2) * bn2 + bt2));
+    const S cf2 = S(0.5) * (W.a2 + b2 + disc);
+    const S cs2 = cf2 > S(0) ? W.a2 * bn2 / cf2 : S(0);
+    W.cf = sqrt(cf2);
+    W.cs = sqrt(cs2);
+    const S ca = sqrt(bn2);
+    if (disc > S(0)) {
+      const S diff = W.a2 - b2;
+      const S nf = diff >= S(0) ? S(0.5) * (diff + disc) : S(2) * W.a2 * bt2 / (disc - diff);
+      const S ns = diff <= S(0) ? S(0.5) * (disc - diff) : S(2) * W.a2 * bt2 / (disc + diff);
+      W.af = sqrt(fmin(S(1), fmax(S(0), nf / disc)));
+      W.as = sqrt(fmin(S(1), fmax(S(0), ns / disc)));
+    } else {
+      W.af = S(1);
+      W.as = S(0);
+    }
+    if (bt2r > S(0)) {
+      const S ibt = S(1) / sqrt(bt2r);
+      W.by = By * ibt;
+      W.bz = Bz * ibt;
+    } else {
+      W.by = S(0.70710678118654752440);
+      W.bz = S(0.70710678118654752440);
+    }
+    W.sgn = Bn >= S(0) ? S(1) : S(-1);
+    // speeds (f-, a-, s-, e, s+, a+, f+)
+    S lam[7] = {u - W.cf, u - ca, u - W.cs, u, u + W.cs, u + ca, u + W.cf};
+    const S L = ph.alpha_local ? fmax(fmax(fabs(lam[0]), fabs(lam[6])), ch) : Lam;
+    const S hk = L > S(0) ? S(0.5 * ph.k) / L : S(0);
+    // primitive images of the seven-wave flux and of the B_n column of the Jacobian
+    S xF[7], xC[7];
+    xF[0] = F[0];
+    xF[1] = (F[1] - u * F[0]) * irho;
+    xF[2] = (F[2] - v * F[0]) * irho;
+    xF[3] = (F[3] - w * F[0]) * irho;
+    xF[4] = gm1 * (F[4] + S(0.5) * uu * F[0] - (u * F[1] + v * F[2] + w * F[3]) - By * F[6] - Bz * F[7]);
+    xF[5] = F[6];
+    xF[6] = F[7];
+    xC[0] = S(0);
+    xC[1] = -gamma * Bn * irho;
+    xC[2] = -By * irho;
+    xC[3] = -Bz * irho;
+    xC[4] = gm1 * (v * By + w * Bz);
+    xC[5] = -v;
+    xC[6] = -w;
+    S cF[7], cC[7], cD[7];
+    project(W, xF, cF);
+    project(W, xC, cC);
+    const S qp = S(0.5) * (psi + ch * Bn), qm = S(0.5) * (psi - ch * Bn);
+    for (int j = 0; j < 7; ++j) {
+      const S bj = beta_w(lam[j], hk, ph.kinf);
+      const S sj = beta_dd(lam[j], ch, hk, ph.kinf) * qp + beta_dd(lam[j], -ch, hk, ph.kinf) * qm;
+      cD[j] = bj * cF[j] + sj * cC[j];
+    }
+    S y[7];
+    combine(W, cD, y);
+    // back to conserved variables (B_n fixed in the seven-wave block)
+    S D[9];
+    D[0] = y[0];
+    D[1] = u * y[0] + rho * y[1];
+    D[2] = v * y[0] + rho * y[2];
+    D[3] = w * y[0] + rho * y[3];
+    D[4] = y[4] / gm1 + S(0.5) * uu * y[0] + rho * (u * y[1] + v * y[2] + w * y[3]) + By * y[5] + Bz * y[6];
+    D[6] = y[5];
+    D[7] = y[6];
+    const S eta = beta_w(ch, hk, ph.kinf) * ch;
+    D[5] = eta * Bn;
+    D[8] = eta * psi;
+    // scatter from the local frame
+    const int perm[3] = {n, t1, t2};
+    Fg[0] = F[0];
+    Dg[0] = D[0];
+    for (int kk = 0; kk < 3; ++kk) {
+      Fg[1 + perm[kk]] = F[1 + kk];
+      Dg[1 + perm[kk]] = D[1 + kk];
+      Fg[5 + perm[kk]] = F[5 + kk];
+      Dg[5 + perm[kk]] = D[5 + kk];
+    }
+    Fg[4] = F[4];
+    Dg[4] = D[4];
+    Fg[8] = F[8];
+    Dg[8] = D[8];
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Equilibrium populations from U and the per-direction (F, D).
+// 1D order (+xi, 0, -xi); 2D order (+x, -x, 0, +y, -y) (Sec. 3.1, Sec. 3.4).
+// With F+ = F/2 + D and F- = F/2 - D per direction:
+//   moving populations  f = c U + F+/xi  (along +d)  and  f = c U - F-/xi  (along -d),
+//   rest population     f = (1 - 2 D c) U - sum_d (F+ - F-)/xi   (D = lattice dimension).
+// ---------------------------------------------------------------------------
+template <int KIND, int DIM, class S>
+struct Equilibrium {
+  using C = Cell<KIND, DIM, S>;
+  static constexpr int P = C::P;
+  static constexpr int Q = DIM == 1 ? 3 : 5;
+  // feq[q][v]
+  __host__ __device__ static void eval(const S* U, const Phys& ph, S ixi, S Lam, S ch, S (*feq)[C::P]) {
+    const S c = S(ph.c);
+    if (DIM == 1) {
+      S F[P], D[P];
+      C::split(0, U, ph, Lam, ch, F, D);
+      for (int v = 0; v < P; ++v) {
+        const S Fp = S(0.5) * F[v] + D[v];
+        const S Fm = S(0.5) * F[v] - D[v];
+        feq[0][v] = c * U[v] + Fp * ixi;
+        feq[1][v] = (S(1) - S(2) * c) * U[v] - (Fp - Fm) * ixi;
+        feq[2][v] = c * U[v] - Fm * ixi;
+      }
+    } else {
+      S F1[P], D1[P], F2[P], D2[P];
+      C::split(0, U, ph, Lam, ch, F1, D1);
+      C::split(1, U, ph, Lam, ch, F2, D2);
+      for (int v = 0; v < P; ++v) {
+        const S F1p = S(0.5) * F1[v] + D1[v], F1m = S(0.5) * F1[v] - D1[v];
+        const S F2p = S(0.5) * F2[v] + D2[v], F2m = S(0.5) * F2[v] - D2[v];
+        feq[0][v] = c * U[v] + F1p * ixi;
+        feq[1][v] = c * U[v] - F1m * ixi;
+        feq[2][v] = (S(1) - S(4) * c) * U[v] - (F1p + F2p - F1m - F2m) * ixi;
+        feq[3][v] = c * U[v] + F2p * ixi;
+        feq[4][v] = c * U[v] - F2m * ixi;
+      }
+    }
+  }
+};
+
+}  // namespace vklb

@@ -1,0 +1,463 @@
+// Device kernels of the WU-VKLB step for gfx950 (one fused kernel per step).
+//
+// Data layout in HBM: populations as structure of arrays, plane (q, var) of
+// `stride` elements at offset (q * P + var) * stride; cell = j * nx + i.
+// Two population buffers ping-pong by step parity. In the "delta" basis the
+// rest-population plane holds U instead (the rest population is U minus the
+// moving ones), which keeps FP32 rounding relative to the small per-step
+// change of U rather than to U itself.
+//
+// Per-step global quantities (Sec. 3.2 CFL speed, Sec. 5.3 cleaning speed)
+// need the max over every cell of the NEW state. Each workgroup therefore
+// recomputes the collision of a one-cell halo, finishes U^{n+1} of its own
+// cells inside the same kernel, reduces max|lambda| (and max c_f) over its
+// cells and atomically folds it into the solve's accumulators; the last
+// workgroup to finish turns the accumulators into xi^{n+1}, Lambda^{n+1},
+// c_h^{n+1}, t^{n+1} for the next launch and clears them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vklb_cell.hpp"
+
+namespace vklb {
+
+// Device-resident state of one solve. Written only by the last workgroup of a
+// launch; read by every workgroup at the start of the next.
+struct DevState {
+  double t;        // time t^n
+  double xi;       // streaming speed for step n (end-time landing applied)
+  double lam;      // Lambda^n = max |lambda(U^n)| (normalizes the sigmoid)
+  double ch;       // c_h^n (MHD)
+  double T;        // end time (inf: none)
+  long long n;     // step index
+  long long max_steps;
+  int done;        // 1: no more steps
+  int landing;     // 1: step n is the one that lands on T
+  int err;         // 1: a non-physical state was produced
+  int pad0;
+  long long err_step;
+  unsigned long long err_cell;   // min cell index (atomicMin)
+  unsigned long long acc_lam;    // bits of a non-negative double (atomicMax)
+  unsigned long long acc_cf;
+  unsigned int counter;          // finished workgroups of the current launch
+  unsigned int pad1;
+  double pad2[4];
+};
+
+// Everything a kernel needs to know about one solve (passed by value).
+struct SolveDesc {
+  void* fa;
+  void* fb;
+  DevState* st;
+  const double* stage;   // FP64 SoA [p][cells] (init source / moments target)
+  double* partials;      // reduction partials for diagnostics
+  Phys ph;
+  double dx;
+  double nu;
+  double xi_fixed;
+  int xi_mode;           // 0 CFL, 1 fixed
+  int nx, ny;            // ny = 1 in 1D
+  long long stride;      // elements per population plane
+  int bcx, bcy;          // 0 periodic, 1 zero gradient
+  int nblocks;           // workgroups per step launch
+  int band;              // 2D rows per band
+};
+
+__device__ inline int map_index(int x, int n, int bc) {
+  if (x >= 0 && x < n) return x;
+  if (bc == 0) {
+    int r = x % n;
+    return r < 0 ? r + n : r;
+  }
+  return x < 0 ? 0 : n - 1;
+}
+
+// Block id remap so that consecutive logical tiles share an XCD (blocks are
+// dispatched to the 8 XCDs round robin); neighbouring tiles then meet in the
+// same L2 when they re-read each other's halo.
+__device__ inline int xcd_remap(int b, int nb) {
+  const int per = nb / 8, rem = nb % 8;
+  const int xcd = b % 8, idx = b / 8;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+__device__ inline unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
+__device__ inline double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+template <class T>
+__device__ inline T wave_max(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Block max of (a, b) into lane 0 of wave 0; `red` needs 2 * (blockDim/64) doubles.
+__device__ inline void block_max2(double& a, double& b, double* red) {
+  a = wave_max(a);
+  b = wave_max(b);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) { red[wid] = a; red[nw + wid] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < nw; ++w) { a = fmax(a, red[w]); b = fmax(b, red[nw + w]); }
+  }
+}
+
+// Fold a workgroup's maxima into the accumulators; the last workgroup of the
+// launch advances the scalars (Sec. 3.5 flow chart: time update, CFL update
+// of xi from U^{n+1}, landing on the end time) and clears the accumulators.
+// Called by thread 0 only. `is_init` marks the initialization reduction.
+__device__ inline void finish_launch(const SolveDesc& sd, double lam_blk, double cf_blk, bool is_init) {
+  DevState* st = sd.st;
+  atomicMax(&st->acc_lam, dbits(lam_blk));
+  if (sd.ph.ch_factor > 0.0) atomicMax(&st->acc_cf, dbits(cf_blk));
+  __threadfence();
+  const unsigned prev = atomicAdd(&st->counter, 1u);
+  if (prev != (unsigned)sd.nblocks - 1) return;
+  __threadfence();
+  const double lam7 = bitsd(atomicAdd(&st->acc_lam, 0ull));
+  const double cfm = bitsd(atomicAdd(&st->acc_cf, 0ull));
+  atomicExch(&st->acc_lam, 0ull);
+  atomicExch(&st->acc_cf, 0ull);
+  atomicExch(&st->counter, 0u);
+  const double ch = sd.ph.ch_factor > 0.0 ? sd.ph.ch_factor * cfm : 0.0;
+  const double Lam = fmax(lam7, ch);
+  double t;
+  long long n;
+  if (is_init) {
+    t = 0.0;
+    n = 0;
+  } else {
+    t = st->landing ? st->T : st->t + sd.dx / st->xi;
+    n = st->n + 1;
+  }
+  double xi = sd.xi_mode == 0 ? Lam / sd.nu : sd.xi_fixed;
+  const int err = atomicAdd(&st->err, 0);
+  int done = (n >= st->max_steps) || !(t < st->T) || err != 0 || !(xi > 0.0) || !isfinite(xi);
+  int landing = 0;
+  if (!done && isfinite(st->T)) {
+    const double dt = sd.dx / xi;
+    if (t + dt >= st->T - 1e-9 * dt) {
+      xi = sd.dx / (st->T - t);
+      landing = 1;
+    }
+  }
+  if (err != 0 && st->err_step < 0) st->err_step = n;
+  st->t = t;
+  st->n = n;
+  st->xi = xi;
+  st->lam = Lam;
+  st->ch = ch;
+  st->landing = landing;
+  st->done = done;
+  __threadfence();
+}
+
+// Split arithmetic type: the MHD eigen-split always runs in FP64.
+template <int KIND, class T> struct SplitType { using type = T; };
+template <class T> struct SplitType<K_MHD, T> { using type = double; };
+
+template <int KIND, int DIM, class T, bool DELTA>
+struct Kern {
+  static constexpr int P = SysInfo<KIND, DIM>::P;
+  static constexpr int Q = DIM == 1 ? 3 : 5;
+  static constexpr int REST = DIM == 1 ? 1 : 2;
+  using ST = typename SplitType<KIND, T>::type;
+
+  // Load a cell, form U^n and the post-collision populations
+  // f* = f - omega (f - f^eq(U^n)) (Sec. 3.5 collision). In the delta basis
+  // U is loaded and the rest population is not formed.
+  __device__ static inline void collide(const T* __restrict__ src, long long stride, int cell, const Phys& ph,
+                                        double ixi, double Lam, double ch, T (&fs)[Q][P], T (&U)[P]) {
+    T f[Q][P];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int v = 0; v < P; ++v) f[q][v] = src[(long long)(q * P + v) * stride + cell];
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+      if (DELTA) {
+        U[v] = f[REST][v];
+      } else {
+        T s = T(0);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) s += f[q][v];
+        U[v] = s;
+      }
+    }
+    ST Us[P];
+#pragma unroll
+    for (int v = 0; v < P; ++v) Us[v] = ST(U[v]);
+    ST fe[Q][P];
+    Equilibrium<KIND, DIM, ST>::eval(Us, ph, ST(ixi), ST(Lam), ST(ch), fe);
+    const T om = T(ph.omega);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      if (DELTA && q == REST) continue;
+#pragma unroll
+      for (int v = 0; v < P; ++v) fs[q][v] = f[q][v] - om * (f[q][v] - T(fe[q][v]));
+    }
+  }
+
+  // Speeds of a finished cell for the global maxima; flags non-physical states.
+  __device__ static inline void new_state(const SolveDesc& sd, const T (&U)[P], long long cell, double& lam,
+                                          double& cfm) {
+    ST Us[P];
+#pragma unroll
+    for (int v = 0; v < P; ++v) Us[v] = ST(U[v]);
+    ST l, c;
+    Cell<KIND, DIM, ST>::speeds(Us, sd.ph, &l, &c);
+    if (!Cell<KIND, DIM, ST>::admissible(Us, sd.ph)) {
+      atomicOr(&sd.st->err, 1);
+      atomicMin(&sd.st->err_cell, (unsigned long long)cell);
+      l = ST(0);
+      c = ST(0);
+    }
+    lam = fmax(lam, double(l));
+    cfm = fmax(cfm, double(c));
+  }
+};
+
+// ---------------------------------------------------------------------------
+// 1D step: workgroups of 256 lanes own 254 consecutive output cells plus one
+// halo cell on each side whose collision they recompute.
+// ---------------------------------------------------------------------------
+template <int KIND, class T, bool DELTA>
+__global__ void __launch_bounds__(256) k_step1d(const SolveDesc sd) {
+  using K = Kern<KIND, 1, T, DELTA>;
+  constexpr int P = K::P, Q = 3;
+  DevState* st = sd.st;
+  if (st->done) return;
+  const long long n = st->n;
+  const T* __restrict__ src = (const T*)((n & 1) ? sd.fb : sd.fa);
+  T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
+  const double ixi = 1.0 / st->xi, Lam = st->lam, ch = st->ch;
+  const int N = sd.nx;
+  const int tid = threadIdx.x;
+  const int x = blockIdx.x * 254 - 1 + tid;
+  const int xl = map_index(x < N + 1 ? x : N, N, sd.bcx);
+  const long long stride = sd.stride;
+
+  __shared__ T s_plus[P][256], s_minus[P][256];
+  __shared__ double red[8];
+
+  T fs[Q][P], U[P];
+  K::collide(src, stride, xl, sd.ph, ixi, Lam, ch, fs, U);
+#pragma unroll
+  for (int v = 0; v < P; ++v) { s_plus[v][tid] = fs[0][v]; s_minus[v][tid] = fs[2][v]; }
+  __syncthreads();
+
+  double lam = 0.0, cfm = 0.0;
+  if (tid >= 1 && tid <= 254 && x < N) {
+    T Un[P];
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+      const T a = s_plus[v][tid - 1];
+      const T b = s_minus[v][tid + 1];
+      dst[(long long)(0 * P + v) * stride + x] = a;
+      dst[(long long)(2 * P + v) * stride + x] = b;
+      if (DELTA) {
+        Un[v] = U[v] + ((a - fs[0][v]) + (b - fs[2][v]));
+        dst[(long long)(1 * P + v) * stride + x] = Un[v];
+      } else {
+        dst[(long long)(1 * P + v) * stride + x] = fs[1][v];
+        Un[v] = ((T(0) + a) + fs[1][v]) + b;
+      }
+    }
+    K::new_state(sd, Un, x, lam, cfm);
+  }
+  block_max2(lam, cfm, red);
+  if (tid == 0) finish_launch(sd, lam, cfm, false);
+}
+
+// ---------------------------------------------------------------------------
+// 2D step: a workgroup of W lanes owns a strip of W columns and `band` rows and
+// marches up the rows. Row r is collided, its +x/-x populations go through LDS
+// (triple buffered, one barrier per row) to the lanes on either side, and row
+// r-1 is finished with the +y population kept from row r-2 and the -y
+// population of row r. The columns left and right of the strip are collided
+// by wave 0 in batches of 32 rows; the rows below and above the band are
+// collided by the whole workgroup (only their y-moving populations are used).
+// ---------------------------------------------------------------------------
+template <int KIND, class T, bool DELTA, int W>
+__global__ void __launch_bounds__(W) k_step2d(const SolveDesc sd) {
+  using K = Kern<KIND, 2, T, DELTA>;
+  constexpr int P = K::P, Q = 5, REST = 2;
+  DevState* st = sd.st;
+  if (st->done) return;
+  const long long n = st->n;
+  const T* __restrict__ src = (const T*)((n & 1) ? sd.fb : sd.fa);
+  T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
+  const double ixi = 1.0 / st->xi, Lam = st->lam, ch = st->ch;
+  const int nx = sd.nx, ny = sd.ny, H = sd.band;
+  const long long stride = sd.stride;
+  const int nsx = (nx + W - 1) / W;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int sx = b % nsx, sy = b / nsx;
+  const int x0 = sx * W, y0 = sy * H, y1 = min(y0 + H, ny);
+  const int tid = threadIdx.x;
+  const int x = x0 + tid;
+  const int xl = map_index(x < nx + 1 ? x : nx, nx, sd.bcx);
+
+  __shared__ T s_ex[3][2][P][W];      // row slot, (+x, -x), var, lane
+  __shared__ T s_halo[2][2][32][P];   // batch buffer, (left +x, right -x), row, var
+  __shared__ double red[2 * (W / 64)];
+
+  T fs[Q][P], U[P];
+  // Row y0 - 1: only its +y population is used (streams into row y0).
+  T prev4[P];
+  {
+    const int yl = map_index(y0 - 1, ny, sd.bcy);
+    K::collide(src, stride, yl * nx + xl, sd.ph, ixi, Lam, ch, fs, U);
+#pragma unroll
+    for (int v = 0; v < P; ++v) prev4[v] = fs[3][v];
+  }
+  // Values of row r-1 carried into iteration r.
+  T c_rest[P], c4[P], c5[P];
+  double lam = 0.0, cfm = 0.0;
+  for (int r = y0; r <= y1; ++r) {
+    // halo columns for rows [r, r + 32) of the band
+    if (r < y1 && ((r - y0) & 31) == 0 && tid < 64) {
+      const int buf = ((r - y0) >> 5) & 1;
+      const int side = tid >> 5;
+      const int row = r + (tid & 31);
+      if (row < y1) {
+        const int hx = map_index(side == 0 ? x0 - 1 : x0 + W, nx, sd.bcx);
+        T hf[Q][P], hU[P];
+        K::collide(src, stride, row * nx + hx, sd.ph, ixi, Lam, ch, hf, hU);
+#pragma unroll
+        for (int v = 0; v < P; ++v) s_halo[buf][side][tid & 31][v] = side == 0 ? hf[0][v] : hf[1][v];
+      }
+    }
+    // collide row r (r == y1 is the row above the band: only its -y population is used)
+    {
+      const int yl = r < y1 ? r : map_index(y1, ny, sd.bcy);
+      K::collide(src, stride, yl * nx + xl, sd.ph, ixi, Lam, ch, fs, U);
+    }
+    const int slot = r % 3;
+    if (r < y1) {
+#pragma unroll
+      for (int v = 0; v < P; ++v) { s_ex[slot][0][v][tid] = fs[0][v]; s_ex[slot][1][v][tid] = fs[1][v]; }
+    }
+    __syncthreads();
+    if (r > y0 && x < nx) {
+      // finish row r-1
+      const int rr = r - 1;
+      const int ps = rr % 3;
+      const int hb = ((rr - y0) >> 5) & 1, hr = (rr - y0) & 31;
+      const long long cell = (long long)rr * nx + x;
+      T Un[P];
+#pragma unroll
+      for (int v = 0; v < P; ++v) {
+        const T a1 = tid > 0 ? s_ex[ps][0][v][tid - 1] : s_halo[hb][0][hr][v];
+        const T a2 = tid < W - 1 ? s_ex[ps][1][v][tid + 1] : s_halo[hb][1][hr][v];
+        const T a4 = prev4[v];
+        const T a5 = fs[4][v];
+        dst[(long long)(0 * P + v) * stride + cell] = a1;
+        dst[(long long)(1 * P + v) * stride + cell] = a2;
+        dst[(long long)(3 * P + v) * stride + cell] = a4;
+        dst[(long long)(4 * P + v) * stride + cell] = a5;
+        if (DELTA) {
+          const T b1 = s_ex[ps][0][v][tid], b2 = s_ex[ps][1][v][tid];
+          Un[v] = c_rest[v] + (((a1 - b1) + (a2 - b2)) + ((a4 - c4[v]) + (a5 - c5[v])));
+        } else {
+          Un[v] = ((((T(0) + a1) + a2) + c_rest[v]) + a4) + a5;
+        }
+        dst[(long long)(REST * P + v) * stride + cell] = DELTA ? Un[v] : c_rest[v];
+      }
+      K::new_state(sd, Un, cell, lam, cfm);
+    }
+    if (r > y0) {
+#pragma unroll
+      for (int v = 0; v < P; ++v) prev4[v] = c4[v];
+    }
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+      c_rest[v] = DELTA ? U[v] : fs[REST][v];
+      c4[v] = fs[3][v];
+      c5[v] = fs[4][v];
+    }
+  }
+  block_max2(lam, cfm, red);
+  if (tid == 0) finish_launch(sd, lam, cfm, false);
+}
+
+// ---------------------------------------------------------------------------
+// Initialization: (1) reduction of max|lambda| and max c_f over U0 (FP64
+// staging) giving xi^0, Lambda^0, c_h^0; (2) f_q = f_q^eq(U0) (Sec. 3.5).
+// ---------------------------------------------------------------------------
+template <int KIND, int DIM>
+__global__ void __launch_bounds__(256) k_init_reduce(const SolveDesc sd) {
+  constexpr int P = SysInfo<KIND, DIM>::P;
+  __shared__ double red[8];
+  const long long cells = (long long)sd.nx * sd.ny;
+  double lam = 0.0, cfm = 0.0;
+  for (long long c = blockIdx.x * 256ll + threadIdx.x; c < cells; c += (long long)gridDim.x * 256) {
+    double U[P];
+#pragma unroll
+    for (int v = 0; v < P; ++v) U[v] = sd.stage[v * cells + c];
+    double l, f;
+    Cell<KIND, DIM, double>::speeds(U, sd.ph, &l, &f);
+    if (!Cell<KIND, DIM, double>::admissible(U, sd.ph)) {
+      atomicOr(&sd.st->err, 1);
+      atomicMin(&sd.st->err_cell, (unsigned long long)c);
+    }
+    lam = fmax(lam, l);
+    cfm = fmax(cfm, f);
+  }
+  block_max2(lam, cfm, red);
+  if (threadIdx.x == 0) finish_launch(sd, lam, cfm, true);
+}
+
+template <int KIND, int DIM, class T, bool DELTA>
+__global__ void __launch_bounds__(256) k_init_feq(const SolveDesc sd) {
+  using K = Kern<KIND, DIM, T, DELTA>;
+  constexpr int P = K::P, Q = K::Q;
+  using ST = typename K::ST;
+  const DevState* st = sd.st;
+  T* __restrict__ f = (T*)sd.fa;
+  const long long cells = (long long)sd.nx * sd.ny;
+  const double ixi = 1.0 / st->xi;
+  for (long long c = blockIdx.x * 256ll + threadIdx.x; c < cells; c += (long long)gridDim.x * 256) {
+    T U[P];
+    ST Us[P];
+#pragma unroll
+    for (int v = 0; v < P; ++v) { U[v] = T(sd.stage[v * cells + c]); Us[v] = ST(U[v]); }
+    ST fe[Q][P];
+    Equilibrium<KIND, DIM, ST>::eval(Us, sd.ph, ST(ixi), ST(st->lam), ST(st->ch), fe);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int v = 0; v < P; ++v)
+        f[(long long)(q * P + v) * sd.stride + c] = (DELTA && q == K::REST) ? U[v] : T(fe[q][v]);
+  }
+}
+
+// U = sum_q f_q (or the stored U in the delta basis) into the FP64 staging.
+template <int KIND, int DIM, class T, bool DELTA>
+__global__ void __launch_bounds__(256) k_moments(const SolveDesc sd) {
+  using K = Kern<KIND, DIM, T, DELTA>;
+  constexpr int P = K::P, Q = K::Q;
+  const long long n = sd.st->n;
+  const T* __restrict__ f = (const T*)((n & 1) ? sd.fb : sd.fa);
+  double* out = const_cast<double*>(sd.stage);
+  const long long cells = (long long)sd.nx * sd.ny;
+  for (long long c = blockIdx.x * 256ll + threadIdx.x; c < cells; c += (long long)gridDim.x * 256) {
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+      T s;
+      if (DELTA) {
+        s = f[(long long)(K::REST * P + v) * sd.stride + c];
+      } else {
+        s = T(0);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) s += f[(long long)(q * P + v) * sd.stride + c];
+      }
+      out[v * cells + c] = double(s);
+    }
+  }
+}
+
+}  // namespace vklb

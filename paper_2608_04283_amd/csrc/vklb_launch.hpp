@@ -1,0 +1,26 @@
+// Kernel launchers per (system, dimension, precision, basis, strip width).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "vklb_kernels.hpp"
+
+namespace vklb {
+
+typedef hipError_t (*launch_fn)(const SolveDesc&, int grid, hipStream_t);
+
+struct Launchers {
+  launch_fn init_reduce = nullptr;
+  launch_fn init_feq = nullptr;
+  launch_fn step = nullptr;
+  launch_fn moments = nullptr;
+  int block = 256;  // threads per step workgroup
+};
+
+// prec: 0 FP64, 1 FP32; delta: 0/1; width: 2D strip width (64/128/256).
+Launchers launchers_sw(int dim, int prec, int delta, int width);
+Launchers launchers_euler(int dim, int prec, int delta, int width);
+Launchers launchers_mhd(int dim, int prec, int delta, int width);
+Launchers launchers_linear(int dim, int prec, int delta, int width);
+
+}  // namespace vklb

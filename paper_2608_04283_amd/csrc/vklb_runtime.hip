@@ -1,0 +1,636 @@
+// Host runtime behind include/vklb.h: argument checks, workspace layout,
+// kernel dispatch, HIP-graph chunks of step launches, diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/vklb.h"
+#include "vklb_launch.hpp"
+
+using namespace vklb;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+std::mutex g_err_mu;
+std::string g_create_error;
+
+int nvars(int kind, int dim) {
+  switch (kind) {
+    case VKLB_SHALLOW_WATER: return dim + 1;
+    case VKLB_EULER: return dim + 2;
+    case VKLB_MHD_GLM: return 9;
+    case VKLB_LINEAR: return 1;
+  }
+  return 0;
+}
+
+struct Layout {
+  size_t state_off, stage_off, fa_off, fb_off, part_off, total;
+  long long stride;
+  int p, Q;
+  size_t elem;
+};
+
+constexpr int kDiagBlocks = 512;
+
+bool layout_of(const vklb_system* sys, vklb_lattice lat, const vklb_grid* g, vklb_precision prec, Layout* L) {
+  if (!sys || !g) return false;
+  if (g->dim != 1 && g->dim != 2) return false;
+  if ((lat == VKLB_D1Q3) != (g->dim == 1)) return false;
+  const int p = nvars(sys->kind, g->dim);
+  if (p == 0) return false;
+  const long long nx = g->n[0], ny = g->dim == 2 ? g->n[1] : 1;
+  if (nx < 1 || ny < 1 || nx > (1ll << 30) || ny > (1ll << 30)) return false;
+  const long long cells = nx * ny;
+  if (cells > (1ll << 31) - 1) return false;
+  L->p = p;
+  L->Q = g->dim == 1 ? 3 : 5;
+  L->elem = prec == VKLB_FP32 ? 4 : 8;
+  L->stride = (cells + 63) / 64 * 64;
+  const size_t plane = size_t(L->stride) * L->elem;
+  L->state_off = 0;
+  L->stage_off = align_up(sizeof(DevState));
+  L->fa_off = align_up(L->stage_off + size_t(p) * cells * 8);
+  L->fb_off = align_up(L->fa_off + size_t(L->Q) * p * plane);
+  L->part_off = align_up(L->fb_off + size_t(L->Q) * p * plane);
+  L->total = align_up(L->part_off + size_t(kDiagBlocks) * 9 * 2 * 8 + 256);
+  return true;
+}
+
+__global__ void k_totals_partial(const double* __restrict__ U, long long cells, int p, double* __restrict__ part) {
+  // Neumaier partial sums of each field over a grid-stride range, combined per
+  // block in a fixed lane order (deterministic for a fixed grid).
+  __shared__ double ss[256], sc[256];
+  for (int v = 0; v < p; ++v) {
+    double s = 0.0, comp = 0.0;
+    for (long long c = blockIdx.x * 256ll + threadIdx.x; c < cells; c += (long long)gridDim.x * 256) {
+      const double x = U[v * cells + c];
+      const double t = s + x;
+      comp += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+      s = t;
+    }
+    ss[threadIdx.x] = s;
+    sc[threadIdx.x] = comp;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double S = 0.0, C = 0.0;
+      for (int i = 0; i < 256; ++i) {
+        const double x = ss[i];
+        const double t = S + x;
+        C += fabs(S) >= fabs(x) ? (S - t) + x : (x - t) + S;
+        S = t;
+        C += sc[i];
+      }
+      part[(blockIdx.x * 9 + v) * 2 + 0] = S;
+      part[(blockIdx.x * 9 + v) * 2 + 1] = C;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_totals_final(const double* __restrict__ part, int nblk, int p, double* __restrict__ out) {
+  const int v = threadIdx.x;
+  if (v >= p) return;
+  double S = 0.0, C = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    const double x = part[(b * 9 + v) * 2];
+    const double t = S + x;
+    C += fabs(S) >= fabs(x) ? (S - t) + x : (x - t) + S;
+    S = t;
+    C += part[(b * 9 + v) * 2 + 1];
+  }
+  out[v] = S + C;
+}
+
+// max |dBx/dx + dBy/dy| by central differences on the FP64 moments; ghosts
+// follow the boundary rule (periodic wrap or copy of the boundary cell).
+__global__ void k_divb(const double* __restrict__ U, int nx, int ny, double dx, int bcx, int bcy,
+                       unsigned long long* __restrict__ out) {
+  const long long cells = (long long)nx * ny;
+  double m = 0.0;
+  for (long long c = blockIdx.x * 256ll + threadIdx.x; c < cells; c += (long long)gridDim.x * 256) {
+    const int i = int(c % nx), j = int(c / nx);
+    const int ip = map_index(i + 1, nx, bcx), im = map_index(i - 1, nx, bcx);
+    const int jp = map_index(j + 1, ny, bcy), jm = map_index(j - 1, ny, bcy);
+    const double* Bx = U + 5 * cells;
+    const double* By = U + 6 * cells;
+    const double d = (Bx[(long long)j * nx + ip] - Bx[(long long)j * nx + im]) / (2.0 * dx) +
+                     (By[(long long)jp * nx + i] - By[(long long)jm * nx + i]) / (2.0 * dx);
+    m = fmax(m, fabs(d));
+  }
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+}  // namespace
+
+// Trailer of a checkpoint blob (see vklb_state_bytes).
+struct CkptTrailer {
+  unsigned long long magic;
+  int kind, dim, prec, delta;
+  long long nx, ny;
+  double t, xi, lam, ch;
+  long long n;
+  int landing, pad;
+  char reserved[128 - 8 - 16 - 16 - 32 - 8 - 8];
+};
+static_assert(sizeof(CkptTrailer) == 128, "trailer is 128 bytes");
+
+struct vklb_solver {
+  vklb_system sys;
+  vklb_lattice lat;
+  vklb_grid grid;
+  vklb_speed speed;
+  double omega;
+  vklb_bc bc[2];
+  vklb_equilibrium eq;
+  vklb_precision prec;
+  vklb_options opt;
+  Layout L;
+  char* buf = nullptr;
+  bool own_buf = false;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  Launchers K;
+  SolveDesc sd;
+  int step_grid = 0;
+  double T = INFINITY;
+  long long max_steps = (1ll << 62);
+  bool inited = false;
+  int chunk = 64;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+  std::string err;
+  int device = 0;
+  int delta = 0;
+};
+
+namespace {
+
+vklb_status fail(vklb_solver* s, vklb_status st, const std::string& msg) {
+  if (s) s->err = msg;
+  else {
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    g_create_error = msg;
+  }
+  return st;
+}
+
+vklb_status hip_fail(vklb_solver* s, hipError_t e, const char* what) {
+  return fail(s, VKLB_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(s, call)                                    \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return hip_fail((s), e_, #call); \
+  } while (0)
+
+Launchers pick(int kind, int dim, int prec, int delta, int width) {
+  switch (kind) {
+    case VKLB_SHALLOW_WATER: return launchers_sw(dim, prec, delta, width);
+    case VKLB_EULER: return launchers_euler(dim, prec, delta, width);
+    case VKLB_MHD_GLM: return launchers_mhd(dim, prec, delta, width);
+    default: return launchers_linear(dim, prec, delta, width);
+  }
+}
+
+int grid_for_cells(long long cells) {
+  long long g = (cells + 255) / 256;
+  return int(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+}
+
+vklb_status reset_state(vklb_solver* s) {
+  DevState h{};
+  h.t = 0.0;
+  h.T = s->T;
+  h.n = 0;
+  h.max_steps = s->max_steps;
+  h.err_step = -1;
+  h.err_cell = ~0ull;
+  HIPCHK(s, hipMemcpyAsync(s->buf + s->L.state_off, &h, sizeof(h), hipMemcpyHostToDevice, s->stream));
+  return VKLB_OK;
+}
+
+vklb_status launch_steps(vklb_solver* s, hipStream_t st, long long n) {
+  for (long long i = 0; i < n; ++i) HIPCHK(s, s->K.step(s->sd, s->step_grid, st));
+  return VKLB_OK;
+}
+
+vklb_status ensure_graph(vklb_solver* s) {
+  if (s->gexec) return VKLB_OK;
+  if (!s->cap_stream) HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+  HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+  vklb_status st = launch_steps(s, s->cap_stream, s->chunk);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+  if (st != VKLB_OK) return st;
+  if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
+  s->graph = g;
+  HIPCHK(s, hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0));
+  return VKLB_OK;
+}
+
+CkptTrailer make_trailer(const vklb_solver* s) {
+  CkptTrailer tr;
+  memset(&tr, 0, sizeof tr);
+  tr.magic = 0x564b4c4243505431ull;  // "VKLBCPT1"
+  tr.kind = s->sys.kind;
+  tr.dim = s->grid.dim;
+  tr.prec = s->prec;
+  tr.delta = s->delta;
+  tr.nx = s->grid.n[0];
+  tr.ny = s->grid.dim == 2 ? s->grid.n[1] : 1;
+  return tr;
+}
+
+vklb_status read_state(vklb_solver* s, DevState* h) {
+  HIPCHK(s, hipMemcpyAsync(h, s->buf + s->L.state_off, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return VKLB_OK;
+}
+
+vklb_status check_err(vklb_solver* s, const DevState& h) {
+  if (h.err) {
+    char msg[160];
+    snprintf(msg, sizeof msg, "non-physical state produced at step %lld, cell %llu", (long long)h.err_step,
+             (unsigned long long)h.err_cell);
+    return fail(s, VKLB_ERR_NONPHYSICAL, msg);
+  }
+  return VKLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vklb_workspace_bytes(const vklb_system* sys, vklb_lattice lat, const vklb_grid* grid, vklb_precision prec) {
+  Layout L;
+  return layout_of(sys, lat, grid, prec, &L) ? L.total : 0;
+}
+
+vklb_status vklb_create(const vklb_system* sys, vklb_lattice lat, const vklb_grid* grid, const vklb_speed* lambda,
+                        double omega, const vklb_bc bc[2], const vklb_equilibrium* eq, vklb_precision prec,
+                        const vklb_options* opt, void* device_buf, size_t buf_bytes, void* hip_stream,
+                        vklb_solver** out) {
+  if (!out) return fail(nullptr, VKLB_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!sys || !grid || !lambda || !bc || !eq) return fail(nullptr, VKLB_ERR_ARG, "NULL argument");
+  if (sys->kind < VKLB_SHALLOW_WATER || sys->kind > VKLB_LINEAR) return fail(nullptr, VKLB_ERR_ARG, "unknown system");
+  if (lat != VKLB_D1Q3 && lat != VKLB_D2Q5) return fail(nullptr, VKLB_ERR_ARG, "unknown lattice");
+  if (grid->dim != 1 && grid->dim != 2) return fail(nullptr, VKLB_ERR_ARG, "grid dim must be 1 or 2");
+  if ((lat == VKLB_D1Q3) != (grid->dim == 1))
+    return fail(nullptr, VKLB_ERR_ARG, "lattice dimension does not match the grid");
+  if (prec != VKLB_FP64 && prec != VKLB_FP32) return fail(nullptr, VKLB_ERR_ARG, "unknown precision");
+  if (!(omega > 0.0 && omega <= 2.0)) return fail(nullptr, VKLB_ERR_ARG, "omega must be in (0, 2]");
+  if (lambda->mode == VKLB_XI_CFL) {
+    if (!(lambda->nu > 0.0 && lambda->nu <= 1.0)) return fail(nullptr, VKLB_ERR_ARG, "nu must be in (0, 1]");
+  } else if (lambda->mode == VKLB_XI_FIXED) {
+    if (!(lambda->xi > 0.0) || !isfinite(lambda->xi)) return fail(nullptr, VKLB_ERR_ARG, "xi must be > 0");
+  } else {
+    return fail(nullptr, VKLB_ERR_ARG, "unknown speed mode");
+  }
+  if (!(eq->c >= 0.0) || !isfinite(eq->c)) return fail(nullptr, VKLB_ERR_ARG, "c must be >= 0");
+  if (!(eq->k >= 0.0)) return fail(nullptr, VKLB_ERR_ARG, "k must be >= 0");
+  const double dx = (grid->hi[0] - grid->lo[0]) / double(grid->n[0]);
+  if (!(dx > 0.0)) return fail(nullptr, VKLB_ERR_ARG, "hi must exceed lo");
+  if (grid->dim == 2) {
+    const double dy = (grid->hi[1] - grid->lo[1]) / double(grid->n[1]);
+    if (!(fabs(dx - dy) <= 1e-12 * dx)) return fail(nullptr, VKLB_ERR_ARG, "the D2Q5 lattice needs dx == dy");
+  }
+  for (int a = 0; a < grid->dim; ++a)
+    if (bc[a] != VKLB_BC_PERIODIC && bc[a] != VKLB_BC_ZERO_GRADIENT) return fail(nullptr, VKLB_ERR_ARG, "unknown bc");
+  if (sys->kind == VKLB_SHALLOW_WATER && !(sys->g > 0.0)) return fail(nullptr, VKLB_ERR_ARG, "g must be > 0");
+  if ((sys->kind == VKLB_EULER || sys->kind == VKLB_MHD_GLM) && !(sys->gamma > 1.0))
+    return fail(nullptr, VKLB_ERR_ARG, "gamma must be > 1");
+  if (sys->kind == VKLB_MHD_GLM && !(sys->ch_factor > 0.0)) return fail(nullptr, VKLB_ERR_ARG, "ch_factor must be > 0");
+  Layout L;
+  if (!layout_of(sys, lat, grid, prec, &L)) return fail(nullptr, VKLB_ERR_UNSUPPORTED, "grid too large or invalid");
+  if (device_buf && buf_bytes < L.total) return fail(nullptr, VKLB_ERR_OOM, "device buffer smaller than vklb_workspace_bytes");
+  if (device_buf && (reinterpret_cast<uintptr_t>(device_buf) % kAlign) != 0)
+    return fail(nullptr, VKLB_ERR_ARG, "device buffer must be 256-byte aligned");
+
+  vklb_solver* s = new vklb_solver();
+  s->sys = *sys;
+  s->lat = lat;
+  s->grid = *grid;
+  if (grid->dim == 1) s->grid.n[1] = 1;
+  s->speed = *lambda;
+  s->omega = omega;
+  s->bc[0] = bc[0];
+  s->bc[1] = grid->dim == 2 ? bc[1] : bc[0];
+  s->eq = *eq;
+  s->prec = prec;
+  if (opt) s->opt = *opt;
+  else memset(&s->opt, 0, sizeof s->opt);
+  s->L = L;
+  s->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (lambda->mode == VKLB_XI_CFL && eq->c > 0.5 * (1.0 - lambda->nu))
+    s->err = "note: c exceeds (1 - nu)/2, the monotonicity bound of Sec. 4.2";
+  hipError_t e = hipGetDevice(&s->device);
+  if (e != hipSuccess) {
+    delete s;
+    return fail(nullptr, VKLB_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  }
+  if (device_buf) {
+    s->buf = static_cast<char*>(device_buf);
+  } else {
+    e = hipMalloc(&s->buf, L.total);
+    if (e != hipSuccess) {
+      delete s;
+      return fail(nullptr, VKLB_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    s->own_buf = true;
+  }
+  const int delta = s->opt.basis == 0 ? (prec == VKLB_FP32 ? 1 : 0) : (s->opt.basis == 2 ? 1 : 0);
+  int width = s->opt.strip_width;
+  if (width != 64 && width != 128 && width != 256) width = grid->n[0] <= 64 ? 64 : (grid->n[0] <= 128 ? 128 : 256);
+  s->K = pick(sys->kind, grid->dim, prec == VKLB_FP32 ? 1 : 0, delta, width);
+  s->delta = delta;
+  int band = s->opt.band_rows;
+  if (band < 1) band = sys->kind == VKLB_MHD_GLM ? 16 : 32;
+  if (band > 4096) band = 4096;
+  s->chunk = s->opt.graph_chunk == 0 ? 64 : s->opt.graph_chunk;
+
+  SolveDesc& d = s->sd;
+  memset(&d, 0, sizeof d);
+  d.fa = s->buf + L.fa_off;
+  d.fb = s->buf + L.fb_off;
+  d.st = reinterpret_cast<DevState*>(s->buf + L.state_off);
+  d.stage = reinterpret_cast<const double*>(s->buf + L.stage_off);
+  d.partials = reinterpret_cast<double*>(s->buf + L.part_off);
+  d.ph.g = sys->g;
+  d.ph.gamma = sys->gamma;
+  d.ph.ch_factor = sys->kind == VKLB_MHD_GLM ? sys->ch_factor : 0.0;
+  d.ph.adv[0] = sys->adv[0];
+  d.ph.adv[1] = sys->adv[1];
+  d.ph.omega = omega;
+  d.ph.c = eq->c;
+  d.ph.kinf = isinf(eq->k) ? 1 : 0;
+  d.ph.k = d.ph.kinf ? 0.0 : eq->k;
+  d.ph.alpha_local = eq->alpha_local ? 1 : 0;
+  d.dx = dx;
+  d.nu = lambda->nu;
+  d.xi_fixed = lambda->xi;
+  d.xi_mode = lambda->mode == VKLB_XI_CFL ? 0 : 1;
+  d.nx = int(grid->n[0]);
+  d.ny = grid->dim == 2 ? int(grid->n[1]) : 1;
+  d.stride = L.stride;
+  d.bcx = s->bc[0] == VKLB_BC_PERIODIC ? 0 : 1;
+  d.bcy = s->bc[1] == VKLB_BC_PERIODIC ? 0 : 1;
+  d.band = band;
+  if (grid->dim == 1) {
+    s->step_grid = int((d.nx + 253) / 254);
+  } else {
+    s->step_grid = int(((d.nx + width - 1) / width) * ((d.ny + band - 1) / band));
+  }
+  d.nblocks = s->step_grid;
+  *out = s;
+  return VKLB_OK;
+}
+
+vklb_status vklb_set_end(vklb_solver* s, double T, int64_t max_steps) {
+  if (!s) return VKLB_ERR_ARG;
+  if (isnan(T)) return fail(s, VKLB_ERR_ARG, "T is NaN");
+  s->T = T;
+  s->max_steps = max_steps < 0 ? (1ll << 62) : max_steps;
+  return VKLB_OK;
+}
+
+static vklb_status init_from(vklb_solver* s, const double* U0, hipMemcpyKind kind) {
+  if (!s || !U0) return VKLB_ERR_ARG;
+  HIPCHK(s, hipSetDevice(s->device));
+  const long long cells = (long long)s->sd.nx * s->sd.ny;
+  HIPCHK(s, hipMemcpyAsync(const_cast<double*>(s->sd.stage), U0, size_t(s->L.p) * cells * 8, kind, s->stream));
+  vklb_status st = reset_state(s);
+  if (st != VKLB_OK) return st;
+  SolveDesc d = s->sd;
+  d.nblocks = grid_for_cells(cells);
+  HIPCHK(s, s->K.init_reduce(d, d.nblocks, s->stream));
+  HIPCHK(s, s->K.init_feq(d, grid_for_cells(cells), s->stream));
+  s->inited = true;
+  return VKLB_OK;
+}
+
+vklb_status vklb_init(vklb_solver* s, const double* U0_host) { return init_from(s, U0_host, hipMemcpyHostToDevice); }
+
+vklb_status vklb_init_device(vklb_solver* s, const double* U0_device) {
+  return init_from(s, U0_device, hipMemcpyDeviceToDevice);
+}
+
+vklb_status vklb_step(vklb_solver* s, int64_t n) {
+  if (!s) return VKLB_ERR_ARG;
+  if (!s->inited) return fail(s, VKLB_ERR_STATE, "vklb_step before vklb_init");
+  if (n < 0) return fail(s, VKLB_ERR_ARG, "n < 0");
+  if (n == 0) return VKLB_OK;
+  HIPCHK(s, hipSetDevice(s->device));
+  if (!s->ev0) {
+    HIPCHK(s, hipEventCreate(&s->ev0));
+    HIPCHK(s, hipEventCreate(&s->ev1));
+  }
+  HIPCHK(s, hipEventRecord(s->ev0, s->stream));
+  long long rem = n;
+  if (s->chunk > 0 && n >= s->chunk) {
+    vklb_status st = ensure_graph(s);
+    if (st != VKLB_OK) return st;
+    while (rem >= s->chunk) {
+      HIPCHK(s, hipGraphLaunch(s->gexec, s->stream));
+      rem -= s->chunk;
+    }
+  }
+  vklb_status st = launch_steps(s, s->stream, rem);
+  if (st != VKLB_OK) return st;
+  HIPCHK(s, hipEventRecord(s->ev1, s->stream));
+  s->timed = true;
+  return VKLB_OK;
+}
+
+vklb_status vklb_last_step_ms(vklb_solver* s, double* ms) {
+  if (!s || !ms) return VKLB_ERR_ARG;
+  if (!s->timed) return fail(s, VKLB_ERR_STATE, "no timed vklb_step yet");
+  HIPCHK(s, hipEventSynchronize(s->ev1));
+  float f = 0.f;
+  HIPCHK(s, hipEventElapsedTime(&f, s->ev0, s->ev1));
+  *ms = f;
+  return VKLB_OK;
+}
+
+vklb_status vklb_moments(vklb_solver* s, double* U_host, double* t, int64_t* steps) {
+  if (!s) return VKLB_ERR_ARG;
+  if (!s->inited) return fail(s, VKLB_ERR_STATE, "vklb_moments before vklb_init");
+  HIPCHK(s, hipSetDevice(s->device));
+  const long long cells = (long long)s->sd.nx * s->sd.ny;
+  if (U_host) {
+    HIPCHK(s, s->K.moments(s->sd, grid_for_cells(cells), s->stream));
+    HIPCHK(s, hipMemcpyAsync(U_host, s->sd.stage, size_t(s->L.p) * cells * 8, hipMemcpyDeviceToHost, s->stream));
+  }
+  DevState h;
+  vklb_status st = read_state(s, &h);
+  if (st != VKLB_OK) return st;
+  if (t) *t = h.t;
+  if (steps) *steps = h.n;
+  return check_err(s, h);
+}
+
+vklb_status vklb_progress(vklb_solver* s, double* t, int64_t* steps, int* done) {
+  if (!s) return VKLB_ERR_ARG;
+  if (!s->inited) return fail(s, VKLB_ERR_STATE, "vklb_progress before vklb_init");
+  HIPCHK(s, hipSetDevice(s->device));
+  DevState h;
+  vklb_status st = read_state(s, &h);
+  if (st != VKLB_OK) return st;
+  if (t) *t = h.t;
+  if (steps) *steps = h.n;
+  if (done) *done = h.done;
+  return check_err(s, h);
+}
+
+vklb_status vklb_diagnostics(vklb_solver* s, vklb_diag* dg) {
+  if (!s || !dg) return VKLB_ERR_ARG;
+  if (!s->inited) return fail(s, VKLB_ERR_STATE, "vklb_diagnostics before vklb_init");
+  HIPCHK(s, hipSetDevice(s->device));
+  memset(dg, 0, sizeof *dg);
+  const long long cells = (long long)s->sd.nx * s->sd.ny;
+  const int p = s->L.p;
+  HIPCHK(s, s->K.moments(s->sd, grid_for_cells(cells), s->stream));
+  const int nb = int(std::min<long long>(kDiagBlocks, (cells + 255) / 256));
+  hipLaunchKernelGGL(k_totals_partial, dim3(nb), dim3(256), 0, s->stream, s->sd.stage, cells, p, s->sd.partials);
+  HIPCHK(s, hipGetLastError());
+  double* tot_dev = s->sd.partials + kDiagBlocks * 9 * 2;
+  hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, s->stream, s->sd.partials, nb, p, tot_dev);
+  HIPCHK(s, hipGetLastError());
+  unsigned long long* divb = reinterpret_cast<unsigned long long*>(tot_dev + 9);
+  HIPCHK(s, hipMemsetAsync(divb, 0, 8, s->stream));
+  if (s->sys.kind == VKLB_MHD_GLM && s->grid.dim == 2) {
+    hipLaunchKernelGGL(k_divb, dim3(grid_for_cells(cells)), dim3(256), 0, s->stream, s->sd.stage, s->sd.nx, s->sd.ny,
+                       s->sd.dx, s->sd.bcx, s->sd.bcy, divb);
+    HIPCHK(s, hipGetLastError());
+  }
+  double host[10];
+  HIPCHK(s, hipMemcpyAsync(host, tot_dev, sizeof host, hipMemcpyDeviceToHost, s->stream));
+  DevState h;
+  vklb_status st = read_state(s, &h);
+  if (st != VKLB_OK) return st;
+  for (int v = 0; v < p; ++v) dg->totals[v] = host[v];
+  unsigned long long db;
+  memcpy(&db, &host[9], 8);
+  double dbv;
+  memcpy(&dbv, &db, 8);
+  dg->max_div_b = dbv;
+  dg->t = h.t;
+  dg->steps = h.n;
+  dg->xi = h.xi;
+  dg->lambda_max = h.lam;
+  dg->ch = h.ch;
+  dg->done = h.done;
+  dg->nonphysical = h.err;
+  dg->fail_step = h.err ? h.err_step : -1;
+  dg->fail_cell = h.err ? (int64_t)h.err_cell : -1;
+  return VKLB_OK;
+}
+
+size_t vklb_state_bytes(const vklb_solver* s) {
+  if (!s) return 0;
+  return size_t(s->L.Q) * s->L.p * size_t(s->L.stride) * s->L.elem + sizeof(CkptTrailer);
+}
+
+vklb_status vklb_get_state(vklb_solver* s, void* host, double* t, int64_t* steps) {
+  if (!s || !host) return VKLB_ERR_ARG;
+  if (!s->inited) return fail(s, VKLB_ERR_STATE, "vklb_get_state before vklb_init");
+  HIPCHK(s, hipSetDevice(s->device));
+  DevState h;
+  vklb_status st = read_state(s, &h);
+  if (st != VKLB_OK) return st;
+  const size_t pop = vklb_state_bytes(s) - sizeof(CkptTrailer);
+  const char* src = (h.n & 1) ? static_cast<const char*>(s->sd.fb) : static_cast<const char*>(s->sd.fa);
+  HIPCHK(s, hipMemcpyAsync(host, src, pop, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  CkptTrailer tr = make_trailer(s);
+  tr.t = h.t;
+  tr.xi = h.xi;
+  tr.lam = h.lam;
+  tr.ch = h.ch;
+  tr.n = h.n;
+  tr.landing = h.landing;
+  memcpy(static_cast<char*>(host) + pop, &tr, sizeof tr);
+  if (t) *t = h.t;
+  if (steps) *steps = h.n;
+  return check_err(s, h);
+}
+
+vklb_status vklb_set_state(vklb_solver* s, const void* host) {
+  if (!s || !host) return VKLB_ERR_ARG;
+  HIPCHK(s, hipSetDevice(s->device));
+  const size_t pop = vklb_state_bytes(s) - sizeof(CkptTrailer);
+  CkptTrailer tr;
+  memcpy(&tr, static_cast<const char*>(host) + pop, sizeof tr);
+  const CkptTrailer me = make_trailer(s);
+  if (tr.magic != me.magic || tr.kind != me.kind || tr.dim != me.dim || tr.prec != me.prec ||
+      tr.delta != me.delta || tr.nx != me.nx || tr.ny != me.ny || tr.n < 0)
+    return fail(s, VKLB_ERR_ARG, "checkpoint does not belong to a solver of this shape");
+  char* dst = (tr.n & 1) ? static_cast<char*>(s->sd.fb) : static_cast<char*>(s->sd.fa);
+  HIPCHK(s, hipMemcpyAsync(dst, host, pop, hipMemcpyHostToDevice, s->stream));
+  DevState h{};
+  h.t = tr.t;
+  h.xi = tr.xi;
+  h.lam = tr.lam;
+  h.ch = tr.ch;
+  h.T = s->T;
+  h.n = tr.n;
+  h.max_steps = s->max_steps;
+  h.landing = tr.landing;
+  h.done = (tr.n >= s->max_steps) || !(tr.t < s->T);
+  h.err_step = -1;
+  h.err_cell = ~0ull;
+  HIPCHK(s, hipMemcpyAsync(s->buf + s->L.state_off, &h, sizeof(h), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  s->inited = true;
+  return VKLB_OK;
+}
+
+void vklb_destroy(vklb_solver* s) {
+  if (!s) return;
+  (void)hipSetDevice(s->device);
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  else (void)hipDeviceSynchronize();
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  if (s->ev0) (void)hipEventDestroy(s->ev0);
+  if (s->ev1) (void)hipEventDestroy(s->ev1);
+  if (s->own_buf && s->buf) (void)hipFree(s->buf);
+  delete s;
+}
+
+const char* vklb_status_str(vklb_status st) {
+  switch (st) {
+    case VKLB_OK: return "ok";
+    case VKLB_ERR_ARG: return "invalid argument";
+    case VKLB_ERR_UNSUPPORTED: return "unsupported";
+    case VKLB_ERR_OOM: return "out of memory";
+    case VKLB_ERR_DEVICE: return "device error";
+    case VKLB_ERR_NONPHYSICAL: return "non-physical state";
+    case VKLB_ERR_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* vklb_last_error(const vklb_solver* s) {
+  if (s) return s->err.c_str();
+  std::lock_guard<std::mutex> lk(g_err_mu);
+  return g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -66,6 +66,7 @@ class Problem:
     omega: float = 1.0
     c: float = 0.05
     k: float = 2.0
+    alpha_norm: str = "global"    # sigmoid normalized by the global max |lambda| (or "local")
     bc: tuple = ("zero_gradient", "zero_gradient")
     T: float = math.inf
     max_steps: int = 2**62

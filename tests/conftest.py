@@ -19,3 +19,14 @@ def oracle():
     from oracle import oracle as O
     O.build()
     return O
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    """The HIP binding; GPU tests fail (not skip) when the library or the GPU is missing."""
+    from paper_2608_04283_amd import vklb
+    vklb.lib()
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu-marked tests need an MI355X")
+    return vklb

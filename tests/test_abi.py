@@ -1,0 +1,101 @@
+"""The C ABI library loads and exports every entry point include/vklb.h
+declares, and rejects invalid arguments before touching the GPU (no GPU)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_2608_04283_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "vklb.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(vklb_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def vk():
+    from paper_2608_04283_amd import vklb
+    vklb.lib()
+    return vklb
+
+
+def test_library_exports_every_declared_symbol(vk):
+    L = vk.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(vk.EXPORTED)
+
+
+def test_workspace_bytes(vk):
+    P = I.sod(65536)
+    b64 = vk.workspace_bytes(P, "fp64")
+    b32 = vk.workspace_bytes(P, "fp32")
+    pop = 3 * 3 * 65536
+    # two population buffers + FP64 staging of U, plus small state/partials
+    assert b64 >= 2 * pop * 8 + 3 * 65536 * 8 and b64 < 2 * pop * 8 + 3 * 65536 * 8 + (1 << 20)
+    assert b32 >= 2 * pop * 4 + 3 * 65536 * 8 and b32 < b64
+    bad = I.sod(10).with_(dim=2)
+    assert vk.workspace_bytes(bad.with_(n=(10, 0)), "fp64") == 0
+
+
+def create(vk, P, precision="fp64", **over):
+    sysd, lat, grid, speed, eq, bc = vk._structs(P)
+    for k, v in over.items():
+        if k in ("omega", "lat"):
+            continue
+        obj, field = k.split(".")
+        setattr({"sys": sysd, "grid": grid, "speed": speed, "eq": eq}[obj], field, v)
+    if "lat" in over:
+        lat = over["lat"]
+    h = ctypes.c_void_p()
+    r = vk.lib().vklb_create(ctypes.byref(sysd), lat, ctypes.byref(grid), ctypes.byref(speed),
+                             over.get("omega", P.omega), bc, ctypes.byref(eq), vk.PRECISIONS[precision], None, None,
+                             0, None, ctypes.byref(h))
+    return r, vk.lib().vklb_last_error(None).decode()
+
+
+@pytest.mark.parametrize("over,needle", [
+    ({"omega": 0.0}, "omega"),
+    ({"omega": 2.5}, "omega"),
+    ({"speed.nu": 1.5}, "nu"),
+    ({"speed.nu": 0.0}, "nu"),
+    ({"eq.c": -0.1}, "c must"),
+    ({"eq.k": -1.0}, "k must"),
+    ({"sys.gamma": 1.0}, "gamma"),
+])
+def test_invalid_arguments_rejected(vk, over, needle):
+    r, msg = create(vk, I.sod(100), **over)
+    assert r == vk.ERR_ARG and needle in msg
+
+
+def test_lattice_grid_mismatch_and_dx_dy(vk):
+    r, msg = create(vk, I.sod(100), lat=1)
+    assert r == vk.ERR_ARG and "lattice" in msg
+    P = I.quadrants(16, steps=1).with_(n=(16, 8))
+    r, msg = create(vk, P)
+    assert r == vk.ERR_ARG and "dx == dy" in msg
+
+
+def test_status_strings(vk):
+    L = vk.lib()
+    assert L.vklb_status_str(0) == b"ok"
+    assert L.vklb_status_str(vk.ERR_NONPHYSICAL) == b"non-physical state"
+
+
+def test_product_path_never_loads_the_oracle():
+    """The package sources import nothing from oracle/ and read nothing from it."""
+    pkg = os.path.join(ROOT, "paper_2608_04283_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".inc", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                for bad in ("import oracle", "from oracle", "oracle/", "oracle.py", "liboracle", "vklb_oracle"):
+                    assert bad not in txt, (f, bad)

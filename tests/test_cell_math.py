@@ -1,0 +1,142 @@
+"""The per-cell arithmetic of the HIP path (paper_2608_04283_amd/csrc/vklb_cell.hpp),
+compiled for the host, against the oracle on random states (no GPU).
+
+The two sides reach the split by different routes: the oracle takes the
+paper's route (Jacobian, null-space eigenvectors, P^-1 F, weights), the HIP
+path uses closed forms per system. Agreement to rounding pins the closed forms.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+import pytest
+
+from test_oracle_cell import rand_state, cfg, ch_for
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CC = os.path.join(ROOT, "paper_2608_04283_amd", "_cellcheck.so")
+KIND = {"sw": 0, "euler": 1, "mhd": 2, "linear": 3}
+
+
+@pytest.fixture(scope="module")
+def cc():
+    if not os.path.exists(CC):
+        from paper_2608_04283_amd import build
+        build.build_cellcheck()
+    L = ctypes.CDLL(CC)
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.vklb_cc_split.argtypes = [ctypes.c_int] * 4 + [dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
+    L.vklb_cc_feq.argtypes = [ctypes.c_int] * 3 + [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+    L.vklb_cc_speeds.argtypes = [ctypes.c_int] * 3 + [dp, dp, dp, dp]
+    return L
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def prm(g=9.81, gamma=1.4, k=2.0, c=0.05, local=False):
+    kinf = 1.0 if math.isinf(k) else 0.0
+    return np.array([g, gamma, 6.0, 0.7, -0.3, 1.0, c, 0.0 if kinf else k, kinf, 1.0 if local else 0.0])
+
+
+def cc_split(cc, prec, system, dim, d, U, pr, Lam, ch):
+    p = len(U)
+    F, D = np.zeros(p), np.zeros(p)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    r = cc.vklb_cc_split(prec, KIND[system], dim, d, _p(U), _p(pr), Lam, ch, _p(F), _p(D))
+    assert r == p
+    return F, D
+
+
+SYSTEMS = [("sw", 1), ("sw", 2), ("euler", 1), ("euler", 2), ("mhd", 1), ("mhd", 2)]
+
+
+@pytest.mark.parametrize("system,dim", SYSTEMS)
+@pytest.mark.parametrize("k", [2.0, 0.7, math.inf])
+@pytest.mark.parametrize("norm", ["global", "local"])
+def test_split_matches_oracle_fp64(oracle, cc, system, dim, k, norm):
+    O = oracle
+    rng = np.random.default_rng(21)
+    gamma = 2.0 if system == "mhd" else 1.4
+    cf = cfg(O, system, dim, k=k, alpha_norm=norm)
+    pr = prm(gamma=gamma, k=k, local=(norm == "local"))
+    for _ in range(25):
+        U = rand_state(system, dim, rng)
+        ch = ch_for(O, cf, U)
+        Lam = 1.3 * max(np.max(np.abs(O.eigenvalues(cf, d, U, ch))) for d in range(dim))
+        for d in range(dim):
+            Fo = O.flux(cf, d, U, ch)
+            Fpo, Fmo = O.split(cf, d, U, ch, lam=Lam)
+            F, D = cc_split(cc, 8, system, dim, d, U, pr, Lam, ch)
+            sc = np.max(np.abs(Fo)) + 1.0
+            assert np.max(np.abs(F - Fo)) < 1e-14 * sc
+            assert np.max(np.abs((0.5 * F + D) - Fpo)) < 2e-12 * sc
+            assert np.max(np.abs((0.5 * F - D) - Fmo)) < 2e-12 * sc
+
+
+@pytest.mark.parametrize("deg", ["bt0", "bt_small", "triple", "bx0"])
+def test_mhd_split_degenerate_matches_oracle(oracle, cc, deg):
+    O = oracle
+    rng = np.random.default_rng(22)
+    for dim in (1, 2):
+        cf = cfg(O, "mhd", dim)
+        pr = prm(gamma=2.0)
+        for _ in range(10):
+            U = rand_state("mhd", dim, rng, degenerate=deg)
+            ch = ch_for(O, cf, U)
+            Lam = max(np.max(np.abs(O.eigenvalues(cf, d, U, ch))) for d in range(dim))
+            for d in range(dim):
+                Fpo, _ = O.split(cf, d, U, ch, lam=Lam)
+                F, D = cc_split(cc, 8, "mhd", dim, d, U, pr, Lam, ch)
+                sc = np.max(np.abs(F)) + 1.0
+                assert np.max(np.abs((0.5 * F + D) - Fpo)) < 1e-8 * sc
+
+
+@pytest.mark.parametrize("system,dim", SYSTEMS)
+def test_split_fp32_close_to_oracle(oracle, cc, system, dim):
+    O = oracle
+    rng = np.random.default_rng(23)
+    gamma = 2.0 if system == "mhd" else 1.4
+    cf = cfg(O, system, dim)
+    pr = prm(gamma=gamma)
+    for _ in range(25):
+        U = rand_state(system, dim, rng)
+        ch = ch_for(O, cf, U)
+        Lam = max(np.max(np.abs(O.eigenvalues(cf, d, U, ch))) for d in range(dim))
+        for d in range(dim):
+            Fpo, _ = O.split(cf, d, U, ch, lam=Lam)
+            F, D = cc_split(cc, 4, system, dim, d, U, pr, Lam, ch)
+            sc = np.max(np.abs(F)) + 1.0
+            assert np.max(np.abs((0.5 * F + D) - Fpo)) < 3e-5 * sc
+
+
+@pytest.mark.parametrize("system,dim", SYSTEMS)
+def test_feq_and_speeds_match_oracle(oracle, cc, system, dim):
+    O = oracle
+    rng = np.random.default_rng(24)
+    gamma = 2.0 if system == "mhd" else 1.4
+    cf = cfg(O, system, dim)
+    pr = prm(gamma=gamma)
+    Q = 3 if dim == 1 else 5
+    for _ in range(10):
+        U = np.ascontiguousarray(rand_state(system, dim, rng))
+        ch = ch_for(O, cf, U)
+        Lam = max(np.max(np.abs(O.eigenvalues(cf, d, U, ch))) for d in range(dim))
+        xi = Lam / 0.9
+        fo = O.feq(cf, U, xi, ch, lam=Lam)
+        out = np.zeros(Q * len(U))
+        cc.vklb_cc_feq(8, KIND[system], dim, _p(U), _p(pr), xi, Lam, ch, _p(out))
+        assert np.allclose(out.reshape(Q, -1), fo, rtol=1e-12, atol=1e-12 * np.max(np.abs(U)))
+        lam, cfm = np.zeros(1), np.zeros(1)
+        cc.vklb_cc_speeds(8, KIND[system], dim, _p(U), _p(pr), _p(lam), _p(cfm))
+        lam_o, _ = O.global_lambda(cf, U.reshape(-1, 1))
+        if system == "mhd":
+            cf_o = max(O.fast_speed(cf, d, U) for d in range(dim))
+            assert abs(cfm[0] - cf_o) < 1e-13 * cf_o
+            # the seven-wave max, without the cleaning pair
+            seven = max(abs(U[1 + d] / U[0]) + O.fast_speed(cf, d, U) for d in range(dim))
+            assert abs(lam[0] - seven) < 1e-13 * seven
+        else:
+            assert abs(lam[0] - lam_o) < 1e-13 * lam_o

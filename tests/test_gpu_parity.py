@@ -1,0 +1,191 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, element by
+element, at sizes the oracle runs in seconds; grids span several workgroup
+tiles and end in ragged tails. FP64: relative L1 per field <= 1e-12; FP32:
+<= 1e-4 (the tolerances the benchmark targets state).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2608_04283_amd import inputs as I
+from parity_util import rel_l1, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-4}
+
+
+def rect_quadrants(nx, ny, seed, steps, **kw):
+    """Four-quadrant Euler data on a non-square grid with dx == dy."""
+    P = I.quadrants(8, seed=seed, steps=steps, **kw)
+    P = P.with_(n=(nx, ny), hi=(nx / ny, 1.0), name=f"euler2d_rect_{nx}x{ny}")
+    X, Y = I.grid2(nx, ny, P.lo, P.hi)
+    rng = I.SplitMix64(seed)
+    st = [(rng.uniform(0.5, 1.5), rng.uniform(0.3, 1.5), rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5))
+          for _ in range(4)]
+    east, north = X >= 0.5 * nx / ny, Y >= 0.5
+    quad = np.where(north & east, 0, np.where(north, 1, np.where(~east, 2, 3)))
+    S = np.array(st)
+    return P.with_(U0=I.euler_state(S[quad, 0], S[quad, 2], S[quad, 1], P.gamma, v=S[quad, 3]))
+
+
+def linear2d(n, steps, omega):
+    P = I.Problem(name="linear2d", system="linear", dim=2, n=(n, n), adv=(0.6, -0.3), xi_mode="fixed", xi=2.0,
+                  omega=omega, bc=("periodic", "periodic"), max_steps=steps)
+    X, Y = I.grid2(n, n, P.lo, P.hi)
+    return P.with_(U0=np.cos(2 * np.pi * (2 * X + Y)).reshape(1, -1))
+
+
+CASES = {
+    # name: (problem factory, precision, solver options)
+    "sw1d_d1q2_fp64": (lambda: I.dam_break(1000, c=0.5, k=0.0), "fp64", {}),
+    "sw1d_wu_100steps_fp64": (lambda: I.dam_break(1000, max_steps=100), "fp64", {}),
+    "euler1d_sod_fp64": (lambda: I.sod(3000), "fp64", {}),
+    "euler1d_sod_fp32": (lambda: I.sod(3000), "fp32", {}),
+    "euler1d_sod_fp64_delta": (lambda: I.sod(3000), "fp64", {"basis": 2}),
+    "euler1d_sod_fp32_plain": (lambda: I.sod(3000), "fp32", {"basis": 1}),
+    "euler1d_wave_fp64": (lambda: I.smooth_wave(700), "fp64", {}),
+    "euler1d_sod_local_alpha_fp64": (lambda: I.sod(1500, alpha_norm="local"), "fp64", {}),
+    "euler1d_sod_discontinuous_fp64": (lambda: I.sod(1500, c=0.0, k=math.inf, nu=0.5), "fp64", {}),
+    "euler1d_sod_centered_fp64": (lambda: I.sod(1500, c=1.0 / 3.0, k=0.0, nu=0.9 / math.sqrt(1.5)), "fp64", {}),
+    "mhd1d_briowu_fp64": (lambda: I.brio_wu(700), "fp64", {}),
+    "mhd1d_briowu_fp32": (lambda: I.brio_wu(700), "fp32", {}),
+    "sw1d_riemann_omega13_fp64": (lambda: I.random_riemann("sw", 1, 777, seed=5, omega=1.3, max_steps=300,
+                                                          nu=0.5), "fp64", {}),
+    "euler2d_quad_fp64": (lambda: I.quadrants(300, seed=0, steps=60), "fp64", {}),
+    "euler2d_quad_fp32": (lambda: I.quadrants(300, seed=0, steps=60), "fp32", {}),
+    "euler2d_rect_periodic_fp64": (lambda: rect_quadrants(300, 170, 3, 50, bc=("periodic", "periodic")), "fp64",
+                                   {}),
+    "euler2d_rect_mixed_bc_fp32": (lambda: rect_quadrants(300, 170, 4, 50, bc=("periodic", "zero_gradient")),
+                                   "fp32", {}),
+    "euler2d_quad_omega15_fp64": (lambda: I.quadrants(130, seed=2, steps=40, omega=1.5, nu=0.3), "fp64", {}),
+    "mhd2d_ot_fp64": (lambda: I.orszag_tang(96, steps=60), "fp64", {}),
+    "mhd2d_ot_fp32": (lambda: I.orszag_tang(96, steps=60), "fp32", {}),
+    "sw2d_riemann_fp64": (lambda: I.random_riemann("sw", 2, 130, seed=7, max_steps=80), "fp64", {}),
+    "sw2d_riemann_fp32": (lambda: I.random_riemann("sw", 2, 130, seed=7, max_steps=80), "fp32", {}),
+    "mhd2d_riemann_fp32": (lambda: I.random_riemann("mhd", 2, 100, seed=9, max_steps=60), "fp32", {}),
+    "linear2d_omega17_fp64": (lambda: linear2d(70, 40, 1.7), "fp64", {}),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_parity_with_oracle(gpu, oracle, name):
+    factory, prec, opts = CASES[name]
+    P = factory()
+    print(f"[case] {name} n={P.n} prec={prec} opts={opts}", flush=True)
+    ref = run_oracle(oracle, P)
+    assert ref["status"] == 0
+    s = gpu.Solver(P, precision=prec, **opts)
+    s.init()
+    U, t, n = s.run()
+    s.close()
+    if prec == "fp64":
+        assert n == ref["steps"]
+        # t = sum of dx/xi^n; xi^n agrees to the last bits, so t does too
+        assert abs(t - ref["t"]) <= 1e-13 * max(1.0, abs(ref["t"]))
+    else:
+        assert abs(n - ref["steps"]) <= 1
+        assert abs(t - ref["t"]) <= 1e-6 * max(1.0, abs(ref["t"]))
+    err = rel_l1(U, ref["U"])
+    print(f"[case] {name} steps={n} rel_l1={np.array2string(err, precision=2)}", flush=True)
+    assert np.all(err <= TOL[prec]), err
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tile_shapes_give_identical_results(gpu, prec):
+    """No cross-cell float reduction feeds back into the state, so every strip
+    width and band height gives the same bits."""
+    P = rect_quadrants(300, 170, 5, 30)
+    outs = []
+    for w, b in ((256, 32), (128, 8), (64, 64), (256, 17)):
+        s = gpu.Solver(P, precision=prec, strip_width=w, band_rows=b)
+        s.init()
+        outs.append(s.run()[0])
+        s.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_repeat_runs_and_graph_chunks_identical(gpu):
+    P = I.sod(2000, T=0.05)
+    res = []
+    for chunk in (0, 7, -1):
+        s = gpu.Solver(P, precision="fp64", graph_chunk=chunk)
+        s.init()
+        res.append(s.run())
+        s.close()
+    for r in res[1:]:
+        assert np.array_equal(r[0], res[0][0]) and r[1:] == res[0][1:]
+
+
+@pytest.mark.parametrize("system,dim,prec", [("euler", 2, "fp32"), ("mhd", 2, "fp32"), ("sw", 1, "fp64"),
+                                             ("euler", 1, "fp32")])
+def test_constant_state_preserved(gpu, system, dim, prec):
+    n = (300,) if dim == 1 else (130, 130)
+    P = I.constant_state(system, dim, n, seed=3, gamma=2.0 if system == "mhd" else 1.4, max_steps=50)
+    s = gpu.Solver(P, precision=prec)
+    s.init()
+    U, _, _ = s.run()
+    s.close()
+    assert np.all(U == U[:, :1])
+    tol = 1e-13 if prec == "fp64" else 1e-6
+    assert np.allclose(U[:, 0], P.U0[:, 0], rtol=tol, atol=tol)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_periodic_totals_conserved(gpu, prec):
+    """Sec. 4.1: interface fluxes cancel telescopically; the compensated device
+    totals stay at their initial values to rounding."""
+    P = I.orszag_tang(256, steps=200)
+    s = gpu.Solver(P, precision=prec)
+    s.init()
+    d0 = s.diagnostics()
+    s.step(200)
+    d1 = s.diagnostics()
+    s.close()
+    scale = np.abs(P.U0).sum(axis=1) + 1e-3 * np.abs(P.U0).sum()
+    drift = np.abs(d1["totals"] - d0["totals"]) / scale
+    assert np.all(drift <= (1e-13 if prec == "fp64" else 2e-6)), drift
+    assert d0["max_div_b"] < 1e-10
+
+
+def test_checkpoint_resume_is_exact(gpu):
+    P = I.quadrants(200, seed=1, steps=0)
+    P = P.with_(max_steps=2**62)
+    a = gpu.Solver(P, precision="fp32")
+    a.init()
+    a.step(37)
+    buf, t, n = a.get_state()
+    a.step(25)
+    Ua, ta, na = a.moments()
+    a.close()
+    b = gpu.Solver(P, precision="fp32")
+    b.set_state(buf)
+    b.step(25)
+    Ub, tb, nb = b.moments()
+    b.close()
+    assert na == nb == 62 and ta == tb
+    assert np.array_equal(Ua, Ub)
+    c = gpu.Solver(P.with_(n=(201, 200), hi=(201 / 200, 1.0)), precision="fp32")
+    with pytest.raises(gpu.VklbError):
+        c.set_state(np.zeros(c.state_bytes(), dtype=np.uint8))
+    c.close()
+
+
+def test_nonphysical_state_reported(gpu, oracle):
+    """Far past the omega threshold of Sec. 5.4 the Sod tube fails; the device
+    flags it and the synchronizing call returns VKLB_ERR_NONPHYSICAL."""
+    P = I.sod(200, omega=1.95)
+    ref = run_oracle(oracle, P)
+    assert ref["status"] == 1
+    s = gpu.Solver(P, precision="fp64")
+    s.init()
+    s.step(5000)
+    with pytest.raises(gpu.VklbError) as ei:
+        s.moments()
+    assert ei.value.status == gpu.ERR_NONPHYSICAL
+    d = s.diagnostics()
+    s.close()
+    assert d["nonphysical"] == 1 and d["fail_step"] == ref["fail_step"]
+    assert d["fail_cell"] == ref["fail_cell"]
