@@ -146,6 +146,7 @@ def main():
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-also", action="store_true", help="skip the other workloads")
+    ap.add_argument("--no-other-precision", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X (no multi-GPU path)",
@@ -180,7 +181,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline(args.workload)
     extra = {}
     for p2 in precs:
-        if p2 != prec:
+        if p2 != prec and not args.no_other_precision:
             r = time_workload(args.workload, p2, max(1, args.steps // 2), 1)
             extra[p2] = {"value": round(r["value"], 2), "ms_per_solve": round(r["ms_per_solve"], 4),
                          "roofline": r["roofline"]}

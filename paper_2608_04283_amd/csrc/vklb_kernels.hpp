@@ -10,10 +10,12 @@
 // Per-step global quantities (Sec. 3.2 CFL speed, Sec. 5.3 cleaning speed)
 // need the max over every cell of the NEW state. Each workgroup therefore
 // recomputes the collision of a one-cell halo, finishes U^{n+1} of its own
-// cells inside the same kernel, reduces max|lambda| (and max c_f) over its
-// cells and atomically folds it into the solve's accumulators; the last
-// workgroup to finish turns the accumulators into xi^{n+1}, Lambda^{n+1},
-// c_h^{n+1}, t^{n+1} for the next launch and clears them.
+// cells inside the same kernel and stores its block maxima of |lambda| (and
+// c_f) with plain stores into a partials array. The kernel boundary is the
+// global synchronization: every workgroup of the next launch reduces all the
+// partials itself and derives the same xi, Lambda, c_h and end condition.
+// Scalars (t, n) and partials are double buffered by launch parity, so the
+// step needs no fence, no atomic and no "last workgroup" election.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,27 +25,21 @@
 
 namespace vklb {
 
-// Device-resident state of one solve. Written only by the last workgroup of a
-// launch; read by every workgroup at the start of the next.
+// Scalars of one solve between launches. S[p] is read by launches of parity p
+// and written (by workgroup 0) for the next launch, of parity 1 - p.
+struct Scal {
+  double t;      // time t^n
+  long long n;   // step index
+  int done;      // 1: end reached or a non-physical state was seen
+  int pad;
+};
+
 struct DevState {
-  double t;        // time t^n
-  double xi;       // streaming speed for step n (end-time landing applied)
-  double lam;      // Lambda^n = max |lambda(U^n)| (normalizes the sigmoid)
-  double ch;       // c_h^n (MHD)
-  double T;        // end time (inf: none)
-  long long n;     // step index
+  Scal S[2];
+  double T;                       // end time (inf: none)
   long long max_steps;
-  int done;        // 1: no more steps
-  int landing;     // 1: step n is the one that lands on T
-  int err;         // 1: a non-physical state was produced
-  int pad0;
-  long long err_step;
-  unsigned long long err_cell;   // min cell index (atomicMin)
-  unsigned long long acc_lam;    // bits of a non-negative double (atomicMax)
-  unsigned long long acc_cf;
-  unsigned int counter;          // finished workgroups of the current launch
-  unsigned int pad1;
-  double pad2[4];
+  unsigned long long err_word;    // min over detections of (step << 32 | cell); ~0 if none
+  double pad[3];
 };
 
 // Everything a kernel needs to know about one solve (passed by value).
@@ -52,7 +48,7 @@ struct SolveDesc {
   void* fb;
   DevState* st;
   const double* stage;   // FP64 SoA [p][cells] (init source / moments target)
-  double* partials;      // reduction partials for diagnostics
+  double* part;          // block maxima: [parity][lam | cf][nblocks]
   Phys ph;
   double dx;
   double nu;
@@ -61,9 +57,45 @@ struct SolveDesc {
   int nx, ny;            // ny = 1 in 1D
   long long stride;      // elements per population plane
   int bcx, bcy;          // 0 periodic, 1 zero gradient
-  int nblocks;           // workgroups per step launch
+  int nblocks;           // workgroups per step launch (= number of partials)
   int band;              // 2D rows per band
+  int par;               // launch parity
+  int pad;
 };
+
+// Values every workgroup derives at the start of a step.
+struct Step {
+  double t, xi, lam, ch;
+  long long n;
+  int landing, done;
+};
+
+// Sec. 3.5 flow chart, between two launches: cleaning speed c_h = factor * max
+// c_f (Sec. 5.3), Lambda = max |lambda|, xi = Lambda / nu (Sec. 3.2) or the fixed
+// speed, and the end condition; the step that reaches T uses xi = dx / (T - t).
+// Shared by device and host so both derive identical values.
+__host__ __device__ inline Step derive_step(const Scal& S, double T, long long max_steps, bool err, double lam7,
+                                            double cfm, double ch_factor, int xi_mode, double nu, double xi_fixed,
+                                            double dx) {
+  Step r;
+  r.t = S.t;
+  r.n = S.n;
+  r.ch = ch_factor > 0.0 ? ch_factor * cfm : 0.0;
+  r.lam = fmax(lam7, r.ch);
+  r.xi = xi_mode == 0 ? r.lam / nu : xi_fixed;
+  r.landing = 0;
+  r.done = S.done || S.n >= max_steps || !(S.t < T) || err || !(r.xi > 0.0) || !isfinite(r.xi);
+  if (!r.done && isfinite(T)) {
+    const double dt = dx / r.xi;
+    const double tol = 1e-9 * dt;
+    const double thr = T - tol;
+    if (S.t + dt >= thr) {
+      r.xi = dx / (T - S.t);
+      r.landing = 1;
+    }
+  }
+  return r;
+}
 
 __device__ inline int map_index(int x, int n, int bc) {
   if (x >= 0 && x < n) return x;
@@ -83,8 +115,6 @@ __device__ inline int xcd_remap(int b, int nb) {
   return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
-__device__ inline unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
-__device__ inline double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
 
 template <class T>
 __device__ inline T wave_max(T v) {
@@ -105,54 +135,66 @@ __device__ inline void block_max2(double& a, double& b, double* red) {
   }
 }
 
-// Fold a workgroup's maxima into the accumulators; the last workgroup of the
-// launch advances the scalars (Sec. 3.5 flow chart: time update, CFL update
-// of xi from U^{n+1}, landing on the end time) and clears the accumulators.
-// Called by thread 0 only. `is_init` marks the initialization reduction.
-__device__ inline void finish_launch(const SolveDesc& sd, double lam_blk, double cf_blk, bool is_init) {
-  DevState* st = sd.st;
-  atomicMax(&st->acc_lam, dbits(lam_blk));
-  if (sd.ph.ch_factor > 0.0) atomicMax(&st->acc_cf, dbits(cf_blk));
-  __threadfence();
-  const unsigned prev = atomicAdd(&st->counter, 1u);
-  if (prev != (unsigned)sd.nblocks - 1) return;
-  __threadfence();
-  const double lam7 = bitsd(atomicAdd(&st->acc_lam, 0ull));
-  const double cfm = bitsd(atomicAdd(&st->acc_cf, 0ull));
-  atomicExch(&st->acc_lam, 0ull);
-  atomicExch(&st->acc_cf, 0ull);
-  atomicExch(&st->counter, 0u);
-  const double ch = sd.ph.ch_factor > 0.0 ? sd.ph.ch_factor * cfm : 0.0;
-  const double Lam = fmax(lam7, ch);
-  double t;
-  long long n;
-  if (is_init) {
-    t = 0.0;
-    n = 0;
-  } else {
-    t = st->landing ? st->T : st->t + sd.dx / st->xi;
-    n = st->n + 1;
+// Block max of (a, b) broadcast to every lane; `red` needs 2 * (blockDim/64) + 2 doubles.
+__device__ inline void block_max2_all(double& a, double& b, double* red) {
+  a = wave_max(a);
+  b = wave_max(b);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) { red[wid] = a; red[nw + wid] = b; }
+  __syncthreads();
+  for (int w = 0; w < nw; ++w) { a = fmax(a, red[w]); b = fmax(b, red[nw + w]); }
+  __syncthreads();
+}
+
+// Reduce the partials of the previous launch and derive the step scalars.
+__device__ inline Step begin_step(const SolveDesc& sd, double* red) {
+  const double* pl = sd.part + (long long)sd.par * 2 * sd.nblocks;
+  const double* pc = pl + sd.nblocks;
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < sd.nblocks; i += blockDim.x) {
+    a = fmax(a, pl[i]);
+    b = fmax(b, pc[i]);
   }
-  double xi = sd.xi_mode == 0 ? Lam / sd.nu : sd.xi_fixed;
-  const int err = atomicAdd(&st->err, 0);
-  int done = (n >= st->max_steps) || !(t < st->T) || err != 0 || !(xi > 0.0) || !isfinite(xi);
-  int landing = 0;
-  if (!done && isfinite(st->T)) {
-    const double dt = sd.dx / xi;
-    if (t + dt >= st->T - 1e-9 * dt) {
-      xi = sd.dx / (st->T - t);
-      landing = 1;
+  block_max2_all(a, b, red);
+  const DevState* st = sd.st;
+  return derive_step(st->S[sd.par], st->T, st->max_steps, st->err_word != ~0ull, a, b, sd.ph.ch_factor, sd.xi_mode,
+                     sd.nu, sd.xi_fixed, sd.dx);
+}
+
+// End of a step: store this workgroup's maxima for the next launch; workgroup 0
+// advances (t, n) for it, or carries a finished state over unchanged.
+__device__ inline void end_step(const SolveDesc& sd, const Step& S, double lam, double cfm) {
+  const int np = sd.par ^ 1;
+  double* pl = sd.part + (long long)np * 2 * sd.nblocks;
+  if (threadIdx.x == 0) {
+    pl[blockIdx.x] = lam;
+    pl[sd.nblocks + blockIdx.x] = cfm;
+    if (blockIdx.x == 0) {
+      Scal nx;
+      nx.t = S.landing ? sd.st->T : S.t + sd.dx / S.xi;
+      nx.n = S.n + 1;
+      nx.done = 0;
+      nx.pad = 0;
+      sd.st->S[np] = nx;
     }
   }
-  if (err != 0 && st->err_step < 0) st->err_step = n;
-  st->t = t;
-  st->n = n;
-  st->xi = xi;
-  st->lam = Lam;
-  st->ch = ch;
-  st->landing = landing;
-  st->done = done;
-  __threadfence();
+}
+
+// A finished solve: workgroup 0 carries the scalars and the partials (the
+// maxima of the final state) over to the other parity unchanged.
+__device__ inline void carry_done(const SolveDesc& sd, const Step& S) {
+  if (blockIdx.x != 0) return;
+  const double* src = sd.part + (long long)sd.par * 2 * sd.nblocks;
+  double* dst = sd.part + (long long)(sd.par ^ 1) * 2 * sd.nblocks;
+  for (int i = threadIdx.x; i < 2 * sd.nblocks; i += blockDim.x) dst[i] = src[i];
+  if (threadIdx.x == 0) {
+    Scal nx;
+    nx.t = S.t;
+    nx.n = S.n;
+    nx.done = 1;
+    nx.pad = 0;
+    sd.st->S[sd.par ^ 1] = nx;
+  }
 }
 
 // Split arithmetic type: the MHD eigen-split always runs in FP64.
@@ -202,16 +244,15 @@ struct Kern {
   }
 
   // Speeds of a finished cell for the global maxima; flags non-physical states.
-  __device__ static inline void new_state(const SolveDesc& sd, const T (&U)[P], long long cell, double& lam,
-                                          double& cfm) {
+  __device__ static inline void new_state(const SolveDesc& sd, const T (&U)[P], long long cell, long long step,
+                                          double& lam, double& cfm) {
     ST Us[P];
 #pragma unroll
     for (int v = 0; v < P; ++v) Us[v] = ST(U[v]);
     ST l, c;
     Cell<KIND, DIM, ST>::speeds(Us, sd.ph, &l, &c);
     if (!Cell<KIND, DIM, ST>::admissible(Us, sd.ph)) {
-      atomicOr(&sd.st->err, 1);
-      atomicMin(&sd.st->err_cell, (unsigned long long)cell);
+      atomicMin(&sd.st->err_word, ((unsigned long long)step << 32) | (unsigned long long)cell);
       l = ST(0);
       c = ST(0);
     }
@@ -228,12 +269,16 @@ template <int KIND, class T, bool DELTA>
 __global__ void __launch_bounds__(256) k_step1d(const SolveDesc sd) {
   using K = Kern<KIND, 1, T, DELTA>;
   constexpr int P = K::P, Q = 3;
-  DevState* st = sd.st;
-  if (st->done) return;
-  const long long n = st->n;
+  __shared__ double red[10];
+  const Step S = begin_step(sd, red);
+  if (S.done) {
+    carry_done(sd, S);
+    return;
+  }
+  const long long n = S.n;
   const T* __restrict__ src = (const T*)((n & 1) ? sd.fb : sd.fa);
   T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
-  const double ixi = 1.0 / st->xi, Lam = st->lam, ch = st->ch;
+  const double ixi = 1.0 / S.xi, Lam = S.lam, ch = S.ch;
   const int N = sd.nx;
   const int tid = threadIdx.x;
   const int x = blockIdx.x * 254 - 1 + tid;
@@ -241,7 +286,6 @@ __global__ void __launch_bounds__(256) k_step1d(const SolveDesc sd) {
   const long long stride = sd.stride;
 
   __shared__ T s_plus[P][256], s_minus[P][256];
-  __shared__ double red[8];
 
   T fs[Q][P], U[P];
   K::collide(src, stride, xl, sd.ph, ixi, Lam, ch, fs, U);
@@ -266,10 +310,10 @@ __global__ void __launch_bounds__(256) k_step1d(const SolveDesc sd) {
         Un[v] = ((T(0) + a) + fs[1][v]) + b;
       }
     }
-    K::new_state(sd, Un, x, lam, cfm);
+    K::new_state(sd, Un, x, n + 1, lam, cfm);
   }
   block_max2(lam, cfm, red);
-  if (tid == 0) finish_launch(sd, lam, cfm, false);
+  end_step(sd, S, lam, cfm);
 }
 
 // ---------------------------------------------------------------------------
@@ -285,12 +329,16 @@ template <int KIND, class T, bool DELTA, int W>
 __global__ void __launch_bounds__(W) k_step2d(const SolveDesc sd) {
   using K = Kern<KIND, 2, T, DELTA>;
   constexpr int P = K::P, Q = 5, REST = 2;
-  DevState* st = sd.st;
-  if (st->done) return;
-  const long long n = st->n;
+  __shared__ double red[2 * (W / 64) + 2];
+  const Step S = begin_step(sd, red);
+  if (S.done) {
+    carry_done(sd, S);
+    return;
+  }
+  const long long n = S.n;
   const T* __restrict__ src = (const T*)((n & 1) ? sd.fb : sd.fa);
   T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
-  const double ixi = 1.0 / st->xi, Lam = st->lam, ch = st->ch;
+  const double ixi = 1.0 / S.xi, Lam = S.lam, ch = S.ch;
   const int nx = sd.nx, ny = sd.ny, H = sd.band;
   const long long stride = sd.stride;
   const int nsx = (nx + W - 1) / W;
@@ -303,7 +351,6 @@ __global__ void __launch_bounds__(W) k_step2d(const SolveDesc sd) {
 
   __shared__ T s_ex[3][2][P][W];      // row slot, (+x, -x), var, lane
   __shared__ T s_halo[2][2][32][P];   // batch buffer, (left +x, right -x), row, var
-  __shared__ double red[2 * (W / 64)];
 
   T fs[Q][P], U[P];
   // Row y0 - 1: only its +y population is used (streams into row y0).
@@ -367,7 +414,7 @@ __global__ void __launch_bounds__(W) k_step2d(const SolveDesc sd) {
         }
         dst[(long long)(REST * P + v) * stride + cell] = DELTA ? Un[v] : c_rest[v];
       }
-      K::new_state(sd, Un, cell, lam, cfm);
+      K::new_state(sd, Un, cell, n + 1, lam, cfm);
     }
     if (r > y0) {
 #pragma unroll
@@ -381,7 +428,7 @@ __global__ void __launch_bounds__(W) k_step2d(const SolveDesc sd) {
     }
   }
   block_max2(lam, cfm, red);
-  if (tid == 0) finish_launch(sd, lam, cfm, false);
+  end_step(sd, S, lam, cfm);
 }
 
 // ---------------------------------------------------------------------------
@@ -390,8 +437,9 @@ __global__ void __launch_bounds__(W) k_step2d(const SolveDesc sd) {
 // ---------------------------------------------------------------------------
 template <int KIND, int DIM>
 __global__ void __launch_bounds__(256) k_init_reduce(const SolveDesc sd) {
+  // Grid = the step grid: block b writes partial b of parity sd.par.
   constexpr int P = SysInfo<KIND, DIM>::P;
-  __shared__ double red[8];
+  __shared__ double red[10];
   const long long cells = (long long)sd.nx * sd.ny;
   double lam = 0.0, cfm = 0.0;
   for (long long c = blockIdx.x * 256ll + threadIdx.x; c < cells; c += (long long)gridDim.x * 256) {
@@ -401,14 +449,19 @@ __global__ void __launch_bounds__(256) k_init_reduce(const SolveDesc sd) {
     double l, f;
     Cell<KIND, DIM, double>::speeds(U, sd.ph, &l, &f);
     if (!Cell<KIND, DIM, double>::admissible(U, sd.ph)) {
-      atomicOr(&sd.st->err, 1);
-      atomicMin(&sd.st->err_cell, (unsigned long long)c);
+      atomicMin(&sd.st->err_word, (unsigned long long)c);
+      l = 0.0;
+      f = 0.0;
     }
     lam = fmax(lam, l);
     cfm = fmax(cfm, f);
   }
   block_max2(lam, cfm, red);
-  if (threadIdx.x == 0) finish_launch(sd, lam, cfm, true);
+  if (threadIdx.x == 0) {
+    double* pl = sd.part + (long long)sd.par * 2 * sd.nblocks;
+    pl[blockIdx.x] = lam;
+    pl[sd.nblocks + blockIdx.x] = cfm;
+  }
 }
 
 template <int KIND, int DIM, class T, bool DELTA>
@@ -416,17 +469,18 @@ __global__ void __launch_bounds__(256) k_init_feq(const SolveDesc sd) {
   using K = Kern<KIND, DIM, T, DELTA>;
   constexpr int P = K::P, Q = K::Q;
   using ST = typename K::ST;
-  const DevState* st = sd.st;
+  __shared__ double red[10];
+  const Step S = begin_step(sd, red);
   T* __restrict__ f = (T*)sd.fa;
   const long long cells = (long long)sd.nx * sd.ny;
-  const double ixi = 1.0 / st->xi;
+  const double ixi = 1.0 / S.xi;
   for (long long c = blockIdx.x * 256ll + threadIdx.x; c < cells; c += (long long)gridDim.x * 256) {
     T U[P];
     ST Us[P];
 #pragma unroll
     for (int v = 0; v < P; ++v) { U[v] = T(sd.stage[v * cells + c]); Us[v] = ST(U[v]); }
     ST fe[Q][P];
-    Equilibrium<KIND, DIM, ST>::eval(Us, sd.ph, ST(ixi), ST(st->lam), ST(st->ch), fe);
+    Equilibrium<KIND, DIM, ST>::eval(Us, sd.ph, ST(ixi), ST(S.lam), ST(S.ch), fe);
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -440,7 +494,7 @@ template <int KIND, int DIM, class T, bool DELTA>
 __global__ void __launch_bounds__(256) k_moments(const SolveDesc sd) {
   using K = Kern<KIND, DIM, T, DELTA>;
   constexpr int P = K::P, Q = K::Q;
-  const long long n = sd.st->n;
+  const long long n = sd.st->S[sd.par].n;
   const T* __restrict__ f = (const T*)((n & 1) ? sd.fb : sd.fa);
   double* out = const_cast<double*>(sd.stage);
   const long long cells = (long long)sd.nx * sd.ny;

@@ -35,13 +35,19 @@ int nvars(int kind, int dim) {
 }
 
 struct Layout {
-  size_t state_off, stage_off, fa_off, fb_off, part_off, total;
+  size_t state_off, stage_off, fa_off, fb_off, part_off, diag_off, total;
   long long stride;
   int p, Q;
   size_t elem;
 };
 
 constexpr int kDiagBlocks = 512;
+
+// Upper bound of the step grid over every strip width / band height choice.
+long long max_step_blocks(const vklb_grid* g) {
+  if (g->dim == 1) return (g->n[0] + 253) / 254;
+  return ((g->n[0] + 63) / 64) * g->n[1];
+}
 
 bool layout_of(const vklb_system* sys, vklb_lattice lat, const vklb_grid* g, vklb_precision prec, Layout* L) {
   if (!sys || !g) return false;
@@ -63,7 +69,8 @@ bool layout_of(const vklb_system* sys, vklb_lattice lat, const vklb_grid* g, vkl
   L->fa_off = align_up(L->stage_off + size_t(p) * cells * 8);
   L->fb_off = align_up(L->fa_off + size_t(L->Q) * p * plane);
   L->part_off = align_up(L->fb_off + size_t(L->Q) * p * plane);
-  L->total = align_up(L->part_off + size_t(kDiagBlocks) * 9 * 2 * 8 + 256);
+  L->diag_off = align_up(L->part_off + size_t(2) * 2 * max_step_blocks(g) * 8);
+  L->total = align_up(L->diag_off + size_t(kDiagBlocks) * 9 * 2 * 8 + 256);
   return true;
 }
 
@@ -139,9 +146,9 @@ struct CkptTrailer {
   unsigned long long magic;
   int kind, dim, prec, delta;
   long long nx, ny;
-  double t, xi, lam, ch;
+  double t, lam7, cfm, pad0;
   long long n;
-  int landing, pad;
+  int done, pad;
   char reserved[128 - 8 - 16 - 16 - 32 - 8 - 8];
 };
 static_assert(sizeof(CkptTrailer) == 128, "trailer is 128 bytes");
@@ -175,6 +182,7 @@ struct vklb_solver {
   std::string err;
   int device = 0;
   int delta = 0;
+  long long launches = 0;   // step launches since init (selects the parity)
 };
 
 namespace {
@@ -212,20 +220,27 @@ int grid_for_cells(long long cells) {
   return int(g < 1 ? 1 : (g > 4096 ? 4096 : g));
 }
 
-vklb_status reset_state(vklb_solver* s) {
-  DevState h{};
-  h.t = 0.0;
+vklb_status reset_state(vklb_solver* s, double t, long long n, int done) {
+  DevState h;
+  memset(&h, 0, sizeof h);
+  h.S[0].t = t;
+  h.S[0].n = n;
+  h.S[0].done = done;
+  h.S[1] = h.S[0];
   h.T = s->T;
-  h.n = 0;
   h.max_steps = s->max_steps;
-  h.err_step = -1;
-  h.err_cell = ~0ull;
+  h.err_word = ~0ull;
   HIPCHK(s, hipMemcpyAsync(s->buf + s->L.state_off, &h, sizeof(h), hipMemcpyHostToDevice, s->stream));
+  s->launches = 0;
   return VKLB_OK;
 }
 
-vklb_status launch_steps(vklb_solver* s, hipStream_t st, long long n) {
-  for (long long i = 0; i < n; ++i) HIPCHK(s, s->K.step(s->sd, s->step_grid, st));
+vklb_status launch_steps(vklb_solver* s, hipStream_t st, long long n, long long first_launch) {
+  SolveDesc d = s->sd;
+  for (long long i = 0; i < n; ++i) {
+    d.par = int((first_launch + i) & 1);
+    HIPCHK(s, s->K.step(d, s->step_grid, st));
+  }
   return VKLB_OK;
 }
 
@@ -233,7 +248,7 @@ vklb_status ensure_graph(vklb_solver* s) {
   if (s->gexec) return VKLB_OK;
   if (!s->cap_stream) HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
   HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-  vklb_status st = launch_steps(s, s->cap_stream, s->chunk);
+  vklb_status st = launch_steps(s, s->cap_stream, s->chunk, 0);  // parities 0, 1, 0, 1, ...
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
   if (st != VKLB_OK) return st;
@@ -246,7 +261,7 @@ vklb_status ensure_graph(vklb_solver* s) {
 CkptTrailer make_trailer(const vklb_solver* s) {
   CkptTrailer tr;
   memset(&tr, 0, sizeof tr);
-  tr.magic = 0x564b4c4243505431ull;  // "VKLBCPT1"
+  tr.magic = 0x564b4c4243505432ull;  // "VKLBCPT2"
   tr.kind = s->sys.kind;
   tr.dim = s->grid.dim;
   tr.prec = s->prec;
@@ -256,17 +271,43 @@ CkptTrailer make_trailer(const vklb_solver* s) {
   return tr;
 }
 
-vklb_status read_state(vklb_solver* s, DevState* h) {
-  HIPCHK(s, hipMemcpyAsync(h, s->buf + s->L.state_off, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+// Host view of the latest state: scalars, partial maxima and the derived step.
+struct HostView {
+  DevState h;
+  Scal S;
+  double lam7, cfm;
+  Step step;
+  bool err;
+  long long err_step, err_cell;
+};
+
+vklb_status read_view(vklb_solver* s, HostView* v) {
+  const int par = int(s->launches & 1);
+  std::vector<double> part(size_t(2) * s->sd.nblocks);
+  HIPCHK(s, hipMemcpyAsync(&v->h, s->buf + s->L.state_off, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipMemcpyAsync(part.data(), s->sd.part + size_t(par) * 2 * s->sd.nblocks, part.size() * 8,
+                           hipMemcpyDeviceToHost, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
+  v->S = v->h.S[par];
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < s->sd.nblocks; ++i) {
+    a = fmax(a, part[i]);
+    b = fmax(b, part[s->sd.nblocks + i]);
+  }
+  v->lam7 = a;
+  v->cfm = b;
+  v->err = v->h.err_word != ~0ull;
+  v->err_step = v->err ? (long long)(v->h.err_word >> 32) : -1;
+  v->err_cell = v->err ? (long long)(v->h.err_word & 0xffffffffull) : -1;
+  const SolveDesc& d = s->sd;
+  v->step = derive_step(v->S, v->h.T, v->h.max_steps, v->err, a, b, d.ph.ch_factor, d.xi_mode, d.nu, d.xi_fixed, d.dx);
   return VKLB_OK;
 }
 
-vklb_status check_err(vklb_solver* s, const DevState& h) {
-  if (h.err) {
+vklb_status check_err(vklb_solver* s, const HostView& v) {
+  if (v.err) {
     char msg[160];
-    snprintf(msg, sizeof msg, "non-physical state produced at step %lld, cell %llu", (long long)h.err_step,
-             (unsigned long long)h.err_cell);
+    snprintf(msg, sizeof msg, "non-physical state produced at step %lld, cell %lld", v.err_step, v.err_cell);
     return fail(s, VKLB_ERR_NONPHYSICAL, msg);
   }
   return VKLB_OK;
@@ -363,6 +404,7 @@ vklb_status vklb_create(const vklb_system* sys, vklb_lattice lat, const vklb_gri
   if (band < 1) band = sys->kind == VKLB_MHD_GLM ? 16 : 32;
   if (band > 4096) band = 4096;
   s->chunk = s->opt.graph_chunk == 0 ? 64 : s->opt.graph_chunk;
+  if (s->chunk > 0) s->chunk = (s->chunk + 1) / 2 * 2;  // even: replays start on parity 0
 
   SolveDesc& d = s->sd;
   memset(&d, 0, sizeof d);
@@ -370,7 +412,7 @@ vklb_status vklb_create(const vklb_system* sys, vklb_lattice lat, const vklb_gri
   d.fb = s->buf + L.fb_off;
   d.st = reinterpret_cast<DevState*>(s->buf + L.state_off);
   d.stage = reinterpret_cast<const double*>(s->buf + L.stage_off);
-  d.partials = reinterpret_cast<double*>(s->buf + L.part_off);
+  d.part = reinterpret_cast<double*>(s->buf + L.part_off);
   d.ph.g = sys->g;
   d.ph.gamma = sys->gamma;
   d.ph.ch_factor = sys->kind == VKLB_MHD_GLM ? sys->ch_factor : 0.0;
@@ -414,10 +456,10 @@ static vklb_status init_from(vklb_solver* s, const double* U0, hipMemcpyKind kin
   HIPCHK(s, hipSetDevice(s->device));
   const long long cells = (long long)s->sd.nx * s->sd.ny;
   HIPCHK(s, hipMemcpyAsync(const_cast<double*>(s->sd.stage), U0, size_t(s->L.p) * cells * 8, kind, s->stream));
-  vklb_status st = reset_state(s);
+  vklb_status st = reset_state(s, 0.0, 0, 0);
   if (st != VKLB_OK) return st;
   SolveDesc d = s->sd;
-  d.nblocks = grid_for_cells(cells);
+  d.par = 0;
   HIPCHK(s, s->K.init_reduce(d, d.nblocks, s->stream));
   HIPCHK(s, s->K.init_feq(d, grid_for_cells(cells), s->stream));
   s->inited = true;
@@ -442,16 +484,25 @@ vklb_status vklb_step(vklb_solver* s, int64_t n) {
   }
   HIPCHK(s, hipEventRecord(s->ev0, s->stream));
   long long rem = n;
-  if (s->chunk > 0 && n >= s->chunk) {
-    vklb_status st = ensure_graph(s);
+  vklb_status st;
+  if (s->chunk > 0 && n >= s->chunk + 1) {
+    st = ensure_graph(s);
     if (st != VKLB_OK) return st;
+    if (s->launches & 1) {  // the graph starts on parity 0
+      st = launch_steps(s, s->stream, 1, s->launches);
+      if (st != VKLB_OK) return st;
+      s->launches += 1;
+      rem -= 1;
+    }
     while (rem >= s->chunk) {
       HIPCHK(s, hipGraphLaunch(s->gexec, s->stream));
       rem -= s->chunk;
+      s->launches += s->chunk;
     }
   }
-  vklb_status st = launch_steps(s, s->stream, rem);
+  st = launch_steps(s, s->stream, rem, s->launches);
   if (st != VKLB_OK) return st;
+  s->launches += rem;
   HIPCHK(s, hipEventRecord(s->ev1, s->stream));
   s->timed = true;
   return VKLB_OK;
@@ -473,28 +524,30 @@ vklb_status vklb_moments(vklb_solver* s, double* U_host, double* t, int64_t* ste
   HIPCHK(s, hipSetDevice(s->device));
   const long long cells = (long long)s->sd.nx * s->sd.ny;
   if (U_host) {
-    HIPCHK(s, s->K.moments(s->sd, grid_for_cells(cells), s->stream));
+    SolveDesc d = s->sd;
+    d.par = int(s->launches & 1);
+    HIPCHK(s, s->K.moments(d, grid_for_cells(cells), s->stream));
     HIPCHK(s, hipMemcpyAsync(U_host, s->sd.stage, size_t(s->L.p) * cells * 8, hipMemcpyDeviceToHost, s->stream));
   }
-  DevState h;
-  vklb_status st = read_state(s, &h);
+  HostView v;
+  vklb_status st = read_view(s, &v);
   if (st != VKLB_OK) return st;
-  if (t) *t = h.t;
-  if (steps) *steps = h.n;
-  return check_err(s, h);
+  if (t) *t = v.S.t;
+  if (steps) *steps = v.S.n;
+  return check_err(s, v);
 }
 
 vklb_status vklb_progress(vklb_solver* s, double* t, int64_t* steps, int* done) {
   if (!s) return VKLB_ERR_ARG;
   if (!s->inited) return fail(s, VKLB_ERR_STATE, "vklb_progress before vklb_init");
   HIPCHK(s, hipSetDevice(s->device));
-  DevState h;
-  vklb_status st = read_state(s, &h);
+  HostView v;
+  vklb_status st = read_view(s, &v);
   if (st != VKLB_OK) return st;
-  if (t) *t = h.t;
-  if (steps) *steps = h.n;
-  if (done) *done = h.done;
-  return check_err(s, h);
+  if (t) *t = v.S.t;
+  if (steps) *steps = v.S.n;
+  if (done) *done = v.step.done;
+  return check_err(s, v);
 }
 
 vklb_status vklb_diagnostics(vklb_solver* s, vklb_diag* dg) {
@@ -504,12 +557,15 @@ vklb_status vklb_diagnostics(vklb_solver* s, vklb_diag* dg) {
   memset(dg, 0, sizeof *dg);
   const long long cells = (long long)s->sd.nx * s->sd.ny;
   const int p = s->L.p;
-  HIPCHK(s, s->K.moments(s->sd, grid_for_cells(cells), s->stream));
+  SolveDesc dm = s->sd;
+  dm.par = int(s->launches & 1);
+  HIPCHK(s, s->K.moments(dm, grid_for_cells(cells), s->stream));
   const int nb = int(std::min<long long>(kDiagBlocks, (cells + 255) / 256));
-  hipLaunchKernelGGL(k_totals_partial, dim3(nb), dim3(256), 0, s->stream, s->sd.stage, cells, p, s->sd.partials);
+  double* dpart = reinterpret_cast<double*>(s->buf + s->L.diag_off);
+  hipLaunchKernelGGL(k_totals_partial, dim3(nb), dim3(256), 0, s->stream, s->sd.stage, cells, p, dpart);
   HIPCHK(s, hipGetLastError());
-  double* tot_dev = s->sd.partials + kDiagBlocks * 9 * 2;
-  hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, s->stream, s->sd.partials, nb, p, tot_dev);
+  double* tot_dev = dpart + kDiagBlocks * 9 * 2;
+  hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, s->stream, dpart, nb, p, tot_dev);
   HIPCHK(s, hipGetLastError());
   unsigned long long* divb = reinterpret_cast<unsigned long long*>(tot_dev + 9);
   HIPCHK(s, hipMemsetAsync(divb, 0, 8, s->stream));
@@ -520,8 +576,8 @@ vklb_status vklb_diagnostics(vklb_solver* s, vklb_diag* dg) {
   }
   double host[10];
   HIPCHK(s, hipMemcpyAsync(host, tot_dev, sizeof host, hipMemcpyDeviceToHost, s->stream));
-  DevState h;
-  vklb_status st = read_state(s, &h);
+  HostView v;
+  vklb_status st = read_view(s, &v);
   if (st != VKLB_OK) return st;
   for (int v = 0; v < p; ++v) dg->totals[v] = host[v];
   unsigned long long db;
@@ -529,15 +585,15 @@ vklb_status vklb_diagnostics(vklb_solver* s, vklb_diag* dg) {
   double dbv;
   memcpy(&dbv, &db, 8);
   dg->max_div_b = dbv;
-  dg->t = h.t;
-  dg->steps = h.n;
-  dg->xi = h.xi;
-  dg->lambda_max = h.lam;
-  dg->ch = h.ch;
-  dg->done = h.done;
-  dg->nonphysical = h.err;
-  dg->fail_step = h.err ? h.err_step : -1;
-  dg->fail_cell = h.err ? (int64_t)h.err_cell : -1;
+  dg->t = v.S.t;
+  dg->steps = v.S.n;
+  dg->xi = v.step.xi;
+  dg->lambda_max = v.step.lam;
+  dg->ch = v.step.ch;
+  dg->done = v.step.done;
+  dg->nonphysical = v.err ? 1 : 0;
+  dg->fail_step = v.err_step;
+  dg->fail_cell = v.err_cell;
   return VKLB_OK;
 }
 
@@ -550,24 +606,23 @@ vklb_status vklb_get_state(vklb_solver* s, void* host, double* t, int64_t* steps
   if (!s || !host) return VKLB_ERR_ARG;
   if (!s->inited) return fail(s, VKLB_ERR_STATE, "vklb_get_state before vklb_init");
   HIPCHK(s, hipSetDevice(s->device));
-  DevState h;
-  vklb_status st = read_state(s, &h);
+  HostView v;
+  vklb_status st = read_view(s, &v);
   if (st != VKLB_OK) return st;
   const size_t pop = vklb_state_bytes(s) - sizeof(CkptTrailer);
-  const char* src = (h.n & 1) ? static_cast<const char*>(s->sd.fb) : static_cast<const char*>(s->sd.fa);
+  const char* src = (v.S.n & 1) ? static_cast<const char*>(s->sd.fb) : static_cast<const char*>(s->sd.fa);
   HIPCHK(s, hipMemcpyAsync(host, src, pop, hipMemcpyDeviceToHost, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
   CkptTrailer tr = make_trailer(s);
-  tr.t = h.t;
-  tr.xi = h.xi;
-  tr.lam = h.lam;
-  tr.ch = h.ch;
-  tr.n = h.n;
-  tr.landing = h.landing;
+  tr.t = v.S.t;
+  tr.n = v.S.n;
+  tr.lam7 = v.lam7;
+  tr.cfm = v.cfm;
+  tr.done = v.S.done;
   memcpy(static_cast<char*>(host) + pop, &tr, sizeof tr);
-  if (t) *t = h.t;
-  if (steps) *steps = h.n;
-  return check_err(s, h);
+  if (t) *t = v.S.t;
+  if (steps) *steps = v.S.n;
+  return check_err(s, v);
 }
 
 vklb_status vklb_set_state(vklb_solver* s, const void* host) {
@@ -582,19 +637,13 @@ vklb_status vklb_set_state(vklb_solver* s, const void* host) {
     return fail(s, VKLB_ERR_ARG, "checkpoint does not belong to a solver of this shape");
   char* dst = (tr.n & 1) ? static_cast<char*>(s->sd.fb) : static_cast<char*>(s->sd.fa);
   HIPCHK(s, hipMemcpyAsync(dst, host, pop, hipMemcpyHostToDevice, s->stream));
-  DevState h{};
-  h.t = tr.t;
-  h.xi = tr.xi;
-  h.lam = tr.lam;
-  h.ch = tr.ch;
-  h.T = s->T;
-  h.n = tr.n;
-  h.max_steps = s->max_steps;
-  h.landing = tr.landing;
-  h.done = (tr.n >= s->max_steps) || !(tr.t < s->T);
-  h.err_step = -1;
-  h.err_cell = ~0ull;
-  HIPCHK(s, hipMemcpyAsync(s->buf + s->L.state_off, &h, sizeof(h), hipMemcpyHostToDevice, s->stream));
+  vklb_status st = reset_state(s, tr.t, tr.n, tr.done);
+  if (st != VKLB_OK) return st;
+  // The saved maxima stand in for the partials of parity 0 (the max is exact).
+  std::vector<double> part(size_t(2) * s->sd.nblocks, 0.0);
+  part[0] = tr.lam7;
+  part[s->sd.nblocks] = tr.cfm;
+  HIPCHK(s, hipMemcpyAsync(s->sd.part, part.data(), part.size() * 8, hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
   s->inited = true;
   return VKLB_OK;
