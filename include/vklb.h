@@ -180,6 +180,64 @@ vklb_status vklb_set_state(vklb_solver* s, const void* host);
 vklb_status vklb_last_step_ms(vklb_solver* s, double* ms);
 
 void vklb_destroy(vklb_solver* s);
+
+/* ------------------------------------------------------------------------
+ * Serving: a pool of concurrent solves in one device arena.
+ *
+ * Requests are admitted in submission order when their workspace fits in
+ * the arena (continuous batching: admission happens at every vklb_pool_run,
+ * while other solves are in flight). Each round advances every resident
+ * solve by one time step with one batched launch per system class, whose
+ * workgroups run tiles of many solves; the per-tile arithmetic is the same as
+ * vklb_step's, so a solve gives the same bits alone and in a batch.
+ * Finished solves are harvested by vklb_pool_poll, which copies U to the
+ * request's output buffer and frees its memory. Not thread safe.
+ * ------------------------------------------------------------------------ */
+typedef struct vklb_pool vklb_pool;
+
+typedef struct {
+  vklb_system sys;
+  vklb_lattice lat;
+  vklb_grid grid;
+  vklb_speed lambda;
+  double omega;
+  vklb_bc bc[2];
+  vklb_equilibrium eq;
+  double T;             /* end time (INFINITY: none) */
+  int64_t max_steps;    /* step limit (< 0: none); a request needs T or max_steps */
+  const double* U0;     /* host FP64 SoA [p][cells]; copied by vklb_pool_submit */
+  double* U_out;        /* host FP64 SoA [p][cells]; written when the solve completes */
+  uint64_t tag;         /* caller's tag, returned with the completion */
+} vklb_request;
+
+typedef struct {
+  uint64_t ticket;
+  uint64_t tag;
+  vklb_status status;   /* VKLB_OK or VKLB_ERR_NONPHYSICAL */
+  double t;
+  int64_t steps;
+  int64_t fail_step, fail_cell;
+} vklb_completion;
+
+typedef struct {
+  int64_t submitted, admitted, completed, queued, resident;
+  int64_t rounds;
+  size_t arena_bytes, arena_used, arena_peak;
+} vklb_pool_stats;
+
+/* hbm_budget: bytes of the device arena (allocated here); prec: precision of
+ * every solve in the pool; hip_stream may be NULL. */
+vklb_status vklb_pool_create(size_t hbm_budget, vklb_precision prec, void* hip_stream, vklb_pool** out);
+/* Validate and queue a request (VKLB_ERR_OOM if it can never fit the arena). */
+vklb_status vklb_pool_submit(vklb_pool* p, const vklb_request* r, uint64_t* ticket);
+/* Admit queued requests that fit, then enqueue `rounds` rounds (asynchronous). */
+vklb_status vklb_pool_run(vklb_pool* p, int rounds);
+/* Synchronize, harvest finished solves (up to max completions written to out,
+ * count in *n; the rest are kept for the next call) and free their memory. */
+vklb_status vklb_pool_poll(vklb_pool* p, vklb_completion* out, int max, int* n);
+vklb_status vklb_pool_get_stats(const vklb_pool* p, vklb_pool_stats* st);
+void vklb_pool_destroy(vklb_pool* p);
+
 const char* vklb_status_str(vklb_status st);
 const char* vklb_last_error(const vklb_solver* s); /* s may be NULL: last create error */
 

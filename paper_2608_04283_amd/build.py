@@ -26,7 +26,7 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 # depend on which workgroup recomputed a halo cell).
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=on", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
          "-Xclang", "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wno-unused-command-line-argument"]
-LIB_SOURCES = ["k_sw.hip", "k_euler.hip", "k_mhd.hip", "k_linear.hip", "vklb_runtime.hip"]
+LIB_SOURCES = ["k_sw.hip", "k_euler.hip", "k_mhd.hip", "k_linear.hip", "vklb_runtime.hip", "vklb_pool.hip"]
 
 
 def _run(cmd):

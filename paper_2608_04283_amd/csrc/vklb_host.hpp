@@ -1,0 +1,168 @@
+// Host-side helpers shared by the single-solve runtime and the serving pool:
+// workspace layout, argument checks, kernel descriptors, launcher choice.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/vklb.h"
+#include "vklb_launch.hpp"
+
+namespace vklb {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+inline int nvars(int kind, int dim) {
+  switch (kind) {
+    case VKLB_SHALLOW_WATER: return dim + 1;
+    case VKLB_EULER: return dim + 2;
+    case VKLB_MHD_GLM: return 9;
+    case VKLB_LINEAR: return 1;
+  }
+  return 0;
+}
+
+struct Layout {
+  size_t state_off, stage_off, fa_off, fb_off, part_off, diag_off, total;
+  long long stride;
+  int p, Q;
+  size_t elem;
+};
+
+constexpr int kDiagBlocks = 512;
+
+// Upper bound of the step grid over every strip width / band height choice.
+inline long long max_step_blocks(const vklb_grid* g) {
+  if (g->dim == 1) return (g->n[0] + 253) / 254;
+  return ((g->n[0] + 63) / 64) * g->n[1];
+}
+
+inline bool layout_of(const vklb_system* sys, vklb_lattice lat, const vklb_grid* g, vklb_precision prec, Layout* L) {
+  if (!sys || !g) return false;
+  if (g->dim != 1 && g->dim != 2) return false;
+  if ((lat == VKLB_D1Q3) != (g->dim == 1)) return false;
+  const int p = nvars(sys->kind, g->dim);
+  if (p == 0) return false;
+  const long long nx = g->n[0], ny = g->dim == 2 ? g->n[1] : 1;
+  if (nx < 1 || ny < 1 || nx > (1ll << 30) || ny > (1ll << 30)) return false;
+  const long long cells = nx * ny;
+  if (cells > (1ll << 31) - 1) return false;
+  L->p = p;
+  L->Q = g->dim == 1 ? 3 : 5;
+  L->elem = prec == VKLB_FP32 ? 4 : 8;
+  L->stride = (cells + 63) / 64 * 64;
+  const size_t plane = size_t(L->stride) * L->elem;
+  L->state_off = 0;
+  L->stage_off = align_up(sizeof(DevState));
+  L->fa_off = align_up(L->stage_off + size_t(p) * cells * 8);
+  L->fb_off = align_up(L->fa_off + size_t(L->Q) * p * plane);
+  L->part_off = align_up(L->fb_off + size_t(L->Q) * p * plane);
+  L->diag_off = align_up(L->part_off + size_t(2) * 2 * max_step_blocks(g) * 8);
+  L->total = align_up(L->diag_off + size_t(kDiagBlocks) * 9 * 2 * 8 + 256);
+  return true;
+}
+
+
+inline int default_width(long long nx) { return nx <= 64 ? 64 : (nx <= 128 ? 128 : 256); }
+inline int default_band(int kind) { return kind == VKLB_MHD_GLM ? 16 : 32; }
+
+inline int step_grid_of(const vklb_grid* g, int width, int band) {
+  if (g->dim == 1) return int((g->n[0] + 253) / 254);
+  return int(((g->n[0] + width - 1) / width) * ((g->n[1] + band - 1) / band));
+}
+
+// Argument checks of vklb_create (Sec. 2.3 omega range, Sec. 3.2 CFL number,
+// Sec. 3.4 dx == dy). Returns VKLB_OK or an error with a message.
+inline vklb_status validate(const vklb_system* sys, vklb_lattice lat, const vklb_grid* grid, const vklb_speed* lambda,
+                            double omega, const vklb_bc bc[2], const vklb_equilibrium* eq, vklb_precision prec,
+                            std::string* msg) {
+  auto bad = [&](vklb_status st, const char* m) { *msg = m; return st; };
+  if (!sys || !grid || !lambda || !bc || !eq) return bad(VKLB_ERR_ARG, "NULL argument");
+  if (sys->kind < VKLB_SHALLOW_WATER || sys->kind > VKLB_LINEAR) return bad(VKLB_ERR_ARG, "unknown system");
+  if (lat != VKLB_D1Q3 && lat != VKLB_D2Q5) return bad(VKLB_ERR_ARG, "unknown lattice");
+  if (grid->dim != 1 && grid->dim != 2) return bad(VKLB_ERR_ARG, "grid dim must be 1 or 2");
+  if ((lat == VKLB_D1Q3) != (grid->dim == 1)) return bad(VKLB_ERR_ARG, "lattice dimension does not match the grid");
+  if (prec != VKLB_FP64 && prec != VKLB_FP32) return bad(VKLB_ERR_ARG, "unknown precision");
+  if (!(omega > 0.0 && omega <= 2.0)) return bad(VKLB_ERR_ARG, "omega must be in (0, 2]");
+  if (lambda->mode == VKLB_XI_CFL) {
+    if (!(lambda->nu > 0.0 && lambda->nu <= 1.0)) return bad(VKLB_ERR_ARG, "nu must be in (0, 1]");
+  } else if (lambda->mode == VKLB_XI_FIXED) {
+    if (!(lambda->xi > 0.0) || !isfinite(lambda->xi)) return bad(VKLB_ERR_ARG, "xi must be > 0");
+  } else {
+    return bad(VKLB_ERR_ARG, "unknown speed mode");
+  }
+  if (!(eq->c >= 0.0) || !isfinite(eq->c)) return bad(VKLB_ERR_ARG, "c must be >= 0");
+  if (!(eq->k >= 0.0)) return bad(VKLB_ERR_ARG, "k must be >= 0");
+  if (grid->n[0] < 1 || (grid->dim == 2 && grid->n[1] < 1)) return bad(VKLB_ERR_ARG, "empty grid");
+  const double dx = (grid->hi[0] - grid->lo[0]) / double(grid->n[0]);
+  if (!(dx > 0.0)) return bad(VKLB_ERR_ARG, "hi must exceed lo");
+  if (grid->dim == 2) {
+    const double dy = (grid->hi[1] - grid->lo[1]) / double(grid->n[1]);
+    if (!(fabs(dx - dy) <= 1e-12 * dx)) return bad(VKLB_ERR_ARG, "the D2Q5 lattice needs dx == dy");
+  }
+  for (int a = 0; a < grid->dim; ++a)
+    if (bc[a] != VKLB_BC_PERIODIC && bc[a] != VKLB_BC_ZERO_GRADIENT) return bad(VKLB_ERR_ARG, "unknown bc");
+  if (sys->kind == VKLB_SHALLOW_WATER && !(sys->g > 0.0)) return bad(VKLB_ERR_ARG, "g must be > 0");
+  if ((sys->kind == VKLB_EULER || sys->kind == VKLB_MHD_GLM) && !(sys->gamma > 1.0))
+    return bad(VKLB_ERR_ARG, "gamma must be > 1");
+  if (sys->kind == VKLB_MHD_GLM && !(sys->ch_factor > 0.0)) return bad(VKLB_ERR_ARG, "ch_factor must be > 0");
+  Layout L;
+  if (!layout_of(sys, lat, grid, prec, &L)) return bad(VKLB_ERR_UNSUPPORTED, "grid too large or invalid");
+  return VKLB_OK;
+}
+
+// Kernel descriptor of a solve whose workspace starts at `base`.
+inline SolveDesc make_desc(char* base, const Layout& L, const vklb_system* sys, const vklb_grid* grid,
+                           const vklb_speed* lambda, double omega, const vklb_bc bc[2], const vklb_equilibrium* eq,
+                           int width, int band) {
+  SolveDesc d;
+  memset(&d, 0, sizeof d);
+  d.fa = base + L.fa_off;
+  d.fb = base + L.fb_off;
+  d.st = reinterpret_cast<DevState*>(base + L.state_off);
+  d.stage = reinterpret_cast<const double*>(base + L.stage_off);
+  d.part = reinterpret_cast<double*>(base + L.part_off);
+  d.ph.g = sys->g;
+  d.ph.gamma = sys->gamma;
+  d.ph.ch_factor = sys->kind == VKLB_MHD_GLM ? sys->ch_factor : 0.0;
+  d.ph.adv[0] = sys->adv[0];
+  d.ph.adv[1] = sys->adv[1];
+  d.ph.omega = omega;
+  d.ph.c = eq->c;
+  d.ph.kinf = isinf(eq->k) ? 1 : 0;
+  d.ph.k = d.ph.kinf ? 0.0 : eq->k;
+  d.ph.alpha_local = eq->alpha_local ? 1 : 0;
+  d.dx = (grid->hi[0] - grid->lo[0]) / double(grid->n[0]);
+  d.nu = lambda->nu;
+  d.xi_fixed = lambda->xi;
+  d.xi_mode = lambda->mode == VKLB_XI_CFL ? 0 : 1;
+  d.nx = int(grid->n[0]);
+  d.ny = grid->dim == 2 ? int(grid->n[1]) : 1;
+  d.stride = L.stride;
+  d.bcx = bc[0] == VKLB_BC_PERIODIC ? 0 : 1;
+  d.bcy = (grid->dim == 2 ? bc[1] : bc[0]) == VKLB_BC_PERIODIC ? 0 : 1;
+  d.band = band;
+  d.nblocks = step_grid_of(grid, width, band);
+  return d;
+}
+
+inline Launchers pick_launchers(int kind, int dim, int prec, int delta, int width) {
+  switch (kind) {
+    case VKLB_SHALLOW_WATER: return launchers_sw(dim, prec, delta, width);
+    case VKLB_EULER: return launchers_euler(dim, prec, delta, width);
+    case VKLB_MHD_GLM: return launchers_mhd(dim, prec, delta, width);
+    default: return launchers_linear(dim, prec, delta, width);
+  }
+}
+
+inline int grid_for_cells(long long cells) {
+  long long g = (cells + 255) / 256;
+  return int(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+}
+
+}  // namespace vklb

@@ -163,13 +163,13 @@ __device__ inline Step begin_step(const SolveDesc& sd, double* red) {
 
 // End of a step: store this workgroup's maxima for the next launch; workgroup 0
 // advances (t, n) for it, or carries a finished state over unchanged.
-__device__ inline void end_step(const SolveDesc& sd, const Step& S, double lam, double cfm) {
+__device__ inline void end_step(const SolveDesc& sd, const Step& S, int tile, double lam, double cfm) {
   const int np = sd.par ^ 1;
   double* pl = sd.part + (long long)np * 2 * sd.nblocks;
   if (threadIdx.x == 0) {
-    pl[blockIdx.x] = lam;
-    pl[sd.nblocks + blockIdx.x] = cfm;
-    if (blockIdx.x == 0) {
+    pl[tile] = lam;
+    pl[sd.nblocks + tile] = cfm;
+    if (tile == 0) {
       Scal nx;
       nx.t = S.landing ? sd.st->T : S.t + sd.dx / S.xi;
       nx.n = S.n + 1;
@@ -182,8 +182,8 @@ __device__ inline void end_step(const SolveDesc& sd, const Step& S, double lam, 
 
 // A finished solve: workgroup 0 carries the scalars and the partials (the
 // maxima of the final state) over to the other parity unchanged.
-__device__ inline void carry_done(const SolveDesc& sd, const Step& S) {
-  if (blockIdx.x != 0) return;
+__device__ inline void carry_done(const SolveDesc& sd, const Step& S, int tile) {
+  if (tile != 0) return;
   const double* src = sd.part + (long long)sd.par * 2 * sd.nblocks;
   double* dst = sd.part + (long long)(sd.par ^ 1) * 2 * sd.nblocks;
   for (int i = threadIdx.x; i < 2 * sd.nblocks; i += blockDim.x) dst[i] = src[i];
@@ -266,13 +266,13 @@ struct Kern {
 // halo cell on each side whose collision they recompute.
 // ---------------------------------------------------------------------------
 template <int KIND, class T, bool DELTA>
-__global__ void __launch_bounds__(256) k_step1d(const SolveDesc sd) {
+__device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
   using K = Kern<KIND, 1, T, DELTA>;
   constexpr int P = K::P, Q = 3;
   __shared__ double red[10];
   const Step S = begin_step(sd, red);
   if (S.done) {
-    carry_done(sd, S);
+    carry_done(sd, S, tile);
     return;
   }
   const long long n = S.n;
@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(256) k_step1d(const SolveDesc sd) {
   const double ixi = 1.0 / S.xi, Lam = S.lam, ch = S.ch;
   const int N = sd.nx;
   const int tid = threadIdx.x;
-  const int x = blockIdx.x * 254 - 1 + tid;
+  const int x = tile * 254 - 1 + tid;
   const int xl = map_index(x < N + 1 ? x : N, N, sd.bcx);
   const long long stride = sd.stride;
 
@@ -313,7 +313,12 @@ __global__ void __launch_bounds__(256) k_step1d(const SolveDesc sd) {
     K::new_state(sd, Un, x, n + 1, lam, cfm);
   }
   block_max2(lam, cfm, red);
-  end_step(sd, S, lam, cfm);
+  end_step(sd, S, tile, lam, cfm);
+}
+
+template <int KIND, class T, bool DELTA>
+__global__ void __launch_bounds__(256) k_step1d(const SolveDesc sd) {
+  step1d_tile<KIND, T, DELTA>(sd, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -326,13 +331,13 @@ __global__ void __launch_bounds__(256) k_step1d(const SolveDesc sd) {
 // collided by the whole workgroup (only their y-moving populations are used).
 // ---------------------------------------------------------------------------
 template <int KIND, class T, bool DELTA, int W>
-__global__ void __launch_bounds__(W) k_step2d(const SolveDesc sd) {
+__device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   using K = Kern<KIND, 2, T, DELTA>;
   constexpr int P = K::P, Q = 5, REST = 2;
   __shared__ double red[2 * (W / 64) + 2];
   const Step S = begin_step(sd, red);
   if (S.done) {
-    carry_done(sd, S);
+    carry_done(sd, S, tile);
     return;
   }
   const long long n = S.n;
@@ -342,8 +347,7 @@ __global__ void __launch_bounds__(W) k_step2d(const SolveDesc sd) {
   const int nx = sd.nx, ny = sd.ny, H = sd.band;
   const long long stride = sd.stride;
   const int nsx = (nx + W - 1) / W;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int sx = b % nsx, sy = b / nsx;
+  const int sx = tile % nsx, sy = tile / nsx;
   const int x0 = sx * W, y0 = sy * H, y1 = min(y0 + H, ny);
   const int tid = threadIdx.x;
   const int x = x0 + tid;
@@ -428,7 +432,36 @@ __global__ void __launch_bounds__(W) k_step2d(const SolveDesc sd) {
     }
   }
   block_max2(lam, cfm, red);
-  end_step(sd, S, lam, cfm);
+  end_step(sd, S, tile, lam, cfm);
+}
+
+template <int KIND, class T, bool DELTA, int W>
+__global__ void __launch_bounds__(W) k_step2d(const SolveDesc sd) {
+  step2d_tile<KIND, T, DELTA, W>(sd, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// ---------------------------------------------------------------------------
+// Batched step for serving: one launch advances every resident solve of one
+// system class by one time step. Work item i = (solve slot, tile); the tile
+// runs the same code as in the single-solve kernels, so a solve gives the
+// same bits alone and in a batch. Items beyond nwork exit.
+// ---------------------------------------------------------------------------
+struct WorkItem {
+  int slot;
+  int tile;
+};
+
+template <int KIND, int DIM, class T, bool DELTA, int W>
+__global__ void __launch_bounds__(W) k_step_batched(const SolveDesc* __restrict__ descs,
+                                                    const WorkItem* __restrict__ work, const int* __restrict__ nwork,
+                                                    int par) {
+  const int i = blockIdx.x;
+  if (i >= *nwork) return;
+  const WorkItem w = work[i];
+  SolveDesc sd = descs[w.slot];
+  sd.par = par;
+  if constexpr (DIM == 1) step1d_tile<KIND, T, DELTA>(sd, w.tile);
+  else step2d_tile<KIND, T, DELTA, W>(sd, w.tile);
 }
 
 // ---------------------------------------------------------------------------

@@ -8,12 +8,15 @@
 namespace vklb {
 
 typedef hipError_t (*launch_fn)(const SolveDesc&, int grid, hipStream_t);
+typedef hipError_t (*batched_fn)(const SolveDesc* descs, const WorkItem* work, const int* nwork, int par, int grid,
+                                 hipStream_t);
 
 struct Launchers {
   launch_fn init_reduce = nullptr;
   launch_fn init_feq = nullptr;
   launch_fn step = nullptr;
   launch_fn moments = nullptr;
+  batched_fn batched = nullptr;  // serving: tiles of many solves in one launch
   int block = 256;  // threads per step workgroup
 };
 

@@ -1,0 +1,143 @@
+"""Request loop over the serving pool (vklb_pool_*) and the plain baseline.
+
+Batched serving: requests are submitted to the pool at their arrival times;
+between chunks of rounds the pool admits what fits in its HBM arena (the
+others wait in order), advances every resident solve, and hands back the
+finished ones. Latency = completion time - arrival time, on the host clock.
+
+Plain baseline: the same kernels, one solve at a time in arrival order, one
+launch per time step (no batching, no graphs).
+"""
+from __future__ import annotations
+
+import collections
+import concurrent.futures as cf
+import time
+
+import numpy as np
+
+from . import inputs
+from . import vklb
+
+
+def _percentiles(lat):
+    if not lat:
+        return None, None
+    a = np.sort(np.asarray(lat))
+    return float(np.percentile(a, 50)), float(np.percentile(a, 99))
+
+
+class _Prefetch:
+    """Builds the initial states of upcoming requests on worker threads."""
+
+    def __init__(self, requests, window=48, workers=4):
+        self.reqs = list(requests)
+        self.window = window
+        self.ex = cf.ThreadPoolExecutor(max_workers=workers)
+        self.fut = {}
+        self.next = 0
+        self._fill()
+
+    def _fill(self):
+        while self.next < len(self.reqs) and len(self.fut) < self.window:
+            rq = self.reqs[self.next]
+            self.fut[rq.rid] = self.ex.submit(inputs.materialize, rq.problem)
+            self.next += 1
+
+    def get(self, rq):
+        p = self.fut.pop(rq.rid).result()
+        self._fill()
+        return p
+
+    def close(self):
+        self.ex.shutdown(wait=False, cancel_futures=True)
+
+
+def run_batched(requests, budget_bytes, precision="fp32", chunk_rounds=32, realtime=True, keep_results=False):
+    """Serve `requests` (inputs.Request, sorted by arrival) through a pool."""
+    reqs = sorted(requests, key=lambda r: r.arrival)
+    pool = vklb.Pool(budget_bytes, precision)
+    pre = _Prefetch(reqs)
+    pending = collections.deque(reqs)
+    arrival = {}
+    latencies = []
+    results = {}
+    cell_steps = 0
+    n_done = 0
+    nonphysical = 0
+    t0 = time.perf_counter()
+    try:
+        while n_done < len(reqs):
+            now = time.perf_counter() - t0
+            while pending and (not realtime or pending[0].arrival <= now):
+                rq = pending.popleft()
+                prob = pre.get(rq)
+                arrival[rq.rid] = rq.arrival if realtime else 0.0
+                pool.submit(prob, tag=rq.rid)
+            st = pool.stats()
+            if st["resident"] + st["queued"] == 0:
+                if pending:
+                    time.sleep(max(0.0, min(0.01, pending[0].arrival - (time.perf_counter() - t0))))
+                continue
+            pool.run(chunk_rounds)
+            for c in pool.poll():
+                t_done = time.perf_counter() - t0
+                latencies.append(t_done - arrival[c["tag"]])
+                cell_steps += c["problem"].cells * c["steps"]
+                n_done += 1
+                nonphysical += int(c["status"] != 0)
+                if keep_results:
+                    results[c["tag"]] = (c["U"], c["t"], c["steps"], c["status"])
+        makespan = time.perf_counter() - t0
+        stats = pool.stats()
+    finally:
+        pre.close()
+        pool.close()
+    p50, p99 = _percentiles(latencies)
+    return {"mode": "batched", "solves": n_done, "makespan_s": makespan, "solves_per_s": n_done / makespan,
+            "p50_s": p50, "p99_s": p99, "cell_steps": cell_steps, "mcell_steps_per_s": cell_steps / makespan / 1e6,
+            "nonphysical": nonphysical, "arena_peak_bytes": stats["arena_peak"], "rounds": stats["rounds"],
+            "results": results if keep_results else None}
+
+
+def run_plain(requests, precision="fp32", realtime=True, keep_results=False):
+    """One solve at a time in arrival order, one kernel launch per time step."""
+    reqs = sorted(requests, key=lambda r: r.arrival)
+    pre = _Prefetch(reqs)
+    latencies = []
+    results = {}
+    cell_steps = 0
+    t0 = time.perf_counter()
+    try:
+        for rq in reqs:
+            prob = pre.get(rq)
+            now = time.perf_counter() - t0
+            if realtime and rq.arrival > now:
+                time.sleep(rq.arrival - now)
+            s = vklb.Solver(prob, precision=precision, graph_chunk=-1)
+            s.init()
+            U, t, n = s.run()
+            s.close()
+            t_done = time.perf_counter() - t0
+            latencies.append(t_done - (rq.arrival if realtime else 0.0))
+            cell_steps += prob.cells * n
+            if keep_results:
+                results[rq.rid] = (U, t, n, 0)
+        makespan = time.perf_counter() - t0
+    finally:
+        pre.close()
+    p50, p99 = _percentiles(latencies)
+    return {"mode": "plain", "solves": len(reqs), "makespan_s": makespan, "solves_per_s": len(reqs) / makespan,
+            "p50_s": p50, "p99_s": p99, "cell_steps": cell_steps, "mcell_steps_per_s": cell_steps / makespan / 1e6,
+            "results": results if keep_results else None}
+
+
+def with_arrivals(requests, rate, seed=7):
+    """Re-time a request list as a Poisson process of the given rate (per s)."""
+    rng = inputs.SplitMix64(seed)
+    t = 0.0
+    out = []
+    for rq in requests:
+        out.append(inputs.Request(rid=rq.rid, arrival=t, problem=rq.problem, steps=rq.steps))
+        t += rng.exponential(rate)
+    return out

@@ -23,7 +23,8 @@ BCS = {"periodic": 0, "zero_gradient": 1, "outflow": 1}
 
 EXPORTED = ["vklb_workspace_bytes", "vklb_create", "vklb_set_end", "vklb_init", "vklb_init_device", "vklb_step", "vklb_moments",
             "vklb_progress", "vklb_diagnostics", "vklb_state_bytes", "vklb_get_state", "vklb_set_state", "vklb_last_step_ms",
-            "vklb_destroy", "vklb_status_str", "vklb_last_error"]
+            "vklb_destroy", "vklb_status_str", "vklb_last_error", "vklb_pool_create", "vklb_pool_submit",
+            "vklb_pool_run", "vklb_pool_poll", "vklb_pool_get_stats", "vklb_pool_destroy"]
 
 
 class VklbError(RuntimeError):
@@ -60,6 +61,23 @@ class Diag(ctypes.Structure):
                 ("lambda_max", ctypes.c_double), ("ch", ctypes.c_double), ("done", ctypes.c_int),
                 ("nonphysical", ctypes.c_int), ("fail_step", ctypes.c_int64), ("fail_cell", ctypes.c_int64),
                 ("totals", ctypes.c_double * 9), ("max_div_b", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("sys", System), ("lat", ctypes.c_int), ("grid", Grid), ("lambda_", Speed), ("omega", ctypes.c_double),
+                ("bc", ctypes.c_int * 2), ("eq", Equilibrium), ("T", ctypes.c_double), ("max_steps", ctypes.c_int64),
+                ("U0", ctypes.c_void_p), ("U_out", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int), ("t", ctypes.c_double),
+                ("steps", ctypes.c_int64), ("fail_step", ctypes.c_int64), ("fail_cell", ctypes.c_int64)]
+
+
+class PoolStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("resident", ctypes.c_int64), ("rounds", ctypes.c_int64),
+                ("arena_bytes", ctypes.c_size_t), ("arena_used", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t)]
 
 
 _lib = None
@@ -104,6 +122,15 @@ def lib():
     L.vklb_status_str.restype = ctypes.c_char_p
     L.vklb_last_error.argtypes = [vp]
     L.vklb_last_error.restype = ctypes.c_char_p
+    L.vklb_pool_create.argtypes = [ctypes.c_size_t, ctypes.c_int, vp, ctypes.POINTER(vp)]
+    L.vklb_pool_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.vklb_pool_run.argtypes = [vp, ctypes.c_int]
+    L.vklb_pool_poll.argtypes = [vp, ctypes.POINTER(Completion), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    L.vklb_pool_get_stats.argtypes = [vp, ctypes.POINTER(PoolStats)]
+    L.vklb_pool_destroy.argtypes = [vp]
+    L.vklb_pool_destroy.restype = None
+    for name in ("vklb_pool_create", "vklb_pool_submit", "vklb_pool_run", "vklb_pool_poll", "vklb_pool_get_stats"):
+        getattr(L, name).restype = ctypes.c_int
     for name in ("vklb_create", "vklb_set_end", "vklb_init", "vklb_init_device", "vklb_step", "vklb_moments", "vklb_progress",
                  "vklb_diagnostics",
                  "vklb_get_state", "vklb_set_state", "vklb_last_step_ms"):
@@ -257,6 +284,76 @@ class Solver:
             lib().vklb_destroy(self._h)
             self._h = None
         self._buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pool:
+    """Serving pool (vklb_pool_*): continuous batching of many solves."""
+
+    def __init__(self, budget_bytes, precision="fp32", stream=None, use_torch=True):
+        L = lib()
+        sptr = None
+        if use_torch:
+            import torch
+            if not torch.cuda.is_available():
+                raise VklbError(ERR_DEVICE, "no GPU visible to torch")
+            st = stream if stream is not None else torch.cuda.current_stream()
+            sptr = st.cuda_stream
+        h = ctypes.c_void_p()
+        r = L.vklb_pool_create(int(budget_bytes), PRECISIONS[precision], sptr, ctypes.byref(h))
+        if r != OK:
+            raise VklbError(r, "vklb_pool_create failed")
+        self._h = h
+        self._live = {}   # ticket -> (problem, U0, U_out)
+
+    def submit(self, problem, tag=0):
+        sysd, lat, grid, speed, eq, bc = _structs(problem)
+        U0 = np.ascontiguousarray(np.asarray(problem.U0, dtype=np.float64).reshape(problem.p, problem.cells))
+        Uo = np.empty_like(U0)
+        T = problem.T if problem.T is not None else math.inf
+        ms = int(problem.max_steps) if problem.max_steps < 2**62 else -1
+        rq = Request(sysd, lat, grid, speed, float(problem.omega), bc, eq, float(T), ms,
+                     U0.ctypes.data_as(ctypes.c_void_p), Uo.ctypes.data_as(ctypes.c_void_p), int(tag))
+        t = ctypes.c_uint64()
+        r = lib().vklb_pool_submit(self._h, ctypes.byref(rq), ctypes.byref(t))
+        if r != OK:
+            raise VklbError(r, "vklb_pool_submit failed")
+        self._live[t.value] = (problem, U0, Uo)
+        return t.value
+
+    def run(self, rounds):
+        r = lib().vklb_pool_run(self._h, int(rounds))
+        if r != OK:
+            raise VklbError(r, "vklb_pool_run failed")
+
+    def poll(self, max_items=4096):
+        buf = (Completion * max_items)()
+        n = ctypes.c_int()
+        r = lib().vklb_pool_poll(self._h, buf, max_items, ctypes.byref(n))
+        if r != OK:
+            raise VklbError(r, "vklb_pool_poll failed")
+        out = []
+        for i in range(n.value):
+            c = buf[i]
+            prob, _, Uo = self._live.pop(c.ticket)
+            out.append({"ticket": c.ticket, "tag": c.tag, "status": c.status, "t": c.t, "steps": c.steps,
+                        "fail_step": c.fail_step, "fail_cell": c.fail_cell, "U": Uo, "problem": prob})
+        return out
+
+    def stats(self):
+        st = PoolStats()
+        lib().vklb_pool_get_stats(self._h, ctypes.byref(st))
+        return {f: getattr(st, f) for f, _ in PoolStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vklb_pool_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:
