@@ -95,12 +95,20 @@ typedef struct {
 } vklb_equilibrium;
 
 /* Storage/arithmetic precision of the populations. FP32 keeps FP64 for the
- * MHD eigen-split, the time t, the streaming speed and the diagnostics. */
+ * MHD split of directions whose characteristic speeds nearly coincide, for
+ * the time t, the streaming speed and the diagnostics. */
 typedef enum { VKLB_FP64 = 0, VKLB_FP32 = 1 } vklb_precision;
 
 typedef struct {
-  int basis;        /* 0: default (FP64 -> populations, FP32 -> moving populations + U);
-                       1: all Q populations; 2: moving populations + U in the rest slot */
+  int basis;        /* stored basis of a cell:
+                       1: all Q populations;
+                       2: the moving populations and U in the rest slot (U^{n+1} = U^n plus the
+                          streamed differences of the moving populations);
+                       3: as 2 with U held as an FP32 pair hi + lo in one more slot and updated by
+                          an error-free sum, so U's rounding does not build up over many steps
+                          (FP32 only; VKLB_ERR_ARG with FP64);
+                       0: default: FP64 -> 1; FP32 -> 3 in 1D, 2 in 2D.
+                       Other values: VKLB_ERR_ARG. */
   int band_rows;    /* 2D: rows per workgroup band (8..64); 0 = tuned default */
   int graph_chunk;  /* steps captured per HIP graph (0 = 64; < 0: plain launches) */
   int strip_width;  /* 2D: columns per workgroup (64, 128 or 256); 0 = tuned default */
@@ -123,7 +131,8 @@ typedef struct {
 } vklb_diag;
 
 /* Bytes of device memory a solve needs (state, FP64 staging of U, two
- * population buffers, reduction partials). 0 if the arguments are invalid. */
+ * population buffers, reduction partials), for the largest stored basis of the
+ * precision, so it suffices for any vklb_options. 0 if the arguments are invalid. */
 size_t vklb_workspace_bytes(const vklb_system* sys, vklb_lattice lat, const vklb_grid* grid, vklb_precision prec);
 
 /* Create a solver. device_buf (>= vklb_workspace_bytes, 256-byte aligned) may be
@@ -166,7 +175,7 @@ vklb_status vklb_progress(vklb_solver* s, double* t, int64_t* steps, int* done);
 vklb_status vklb_diagnostics(vklb_solver* s, vklb_diag* d);
 
 /* Checkpoint / resume. The blob (vklb_state_bytes bytes) holds the stored
- * population planes ([q][var][cell], the solver's precision and basis)
+ * population planes ([slot][var][cell], the solver's precision and basis)
  * followed by a 128-byte trailer with t, the step count, xi, Lambda, c_h, the
  * end-time landing flag and the solve's shape. vklb_set_state restores all of
  * it, so a resumed run continues bit for bit; it rejects (VKLB_ERR_ARG) a blob

@@ -19,7 +19,9 @@
 //     seven-wave block uses Roe-Balsara normalized primitive eigenvectors
 //     (well defined at coinciding speeds); the coupling through C uses divided
 //     differences of beta between each seven-wave speed and +-c_h; on the
-//     cleaning pair D = beta(c_h) c_h (B_n, psi).
+//     cleaning pair D = beta(c_h) c_h (B_n, psi). In FP32, the eigenstructure
+//     (speeds and normalization) of directions whose speeds nearly coincide is
+//     evaluated in FP64.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -59,15 +61,14 @@ __host__ __device__ inline S beta_w(S lam, S half_k_over_L, int kinf) {
   return S(0.5) * tanh(lam * half_k_over_L);
 }
 
-// Divided difference (beta(a) - beta(b)) / (a - b), with the derivative when
-// the two speeds (nearly) coincide.
+// Divided difference (beta(a) - beta(b)) / (a - b) from the weights ba, bb
+// already evaluated, with the derivative when the two speeds nearly coincide.
 template <class S>
-__host__ __device__ inline S beta_dd(S a, S b, S half_k_over_L, int kinf) {
-  S d = a - b;
-  S ba = beta_w(a, half_k_over_L, kinf), bb = beta_w(b, half_k_over_L, kinf);
+__host__ __device__ inline S beta_dd(S a, S ba, S b, S bb, S half_k_over_L, int kinf) {
+  const S d = a - b;
   const S rel = sizeof(S) == 4 ? S(1e-3) : S(1e-6);
   if (fabs(d) > rel * (fabs(a) + fabs(b)) || kinf) return d != S(0) ? (ba - bb) / d : S(0);
-  S tm = tanh(S(0.5) * (a + b) * half_k_over_L);
+  const S tm = tanh(S(0.5) * (a + b) * half_k_over_L);
   return S(0.5) * half_k_over_L * (S(1) - tm * tm);
 }
 
@@ -274,6 +275,61 @@ struct Cell<K_MHD, DIM, S> {
     y[6] = w.bz * bp + w.by * bq;
   }
 
+  // Directions whose MHD speeds nearly coincide: the fast and slow speeds
+  // nearly meet (c_f^2 - c_s^2 small) or the transverse or normal field nearly
+  // vanishes. The FP32 split computes their eigenstructure in FP64.
+  __host__ __device__ static bool near_degenerate(int d, const S* U, S gamma) {
+    const S rho = U[0];
+    const S a2 = gamma * pressure(U, gamma) / rho;
+    const S bn2 = U[5 + d] * U[5 + d] / rho;
+    const S bt2 = (U[5] * U[5] + U[6] * U[6] + U[7] * U[7]) / rho - bn2;
+    const S tot = a2 + bn2 + bt2;
+    const S disc2 = sq(a2 - bn2) + bt2 * (S(2) * a2 + S(2) * bn2 + bt2);
+    return disc2 < S(1e-4) * tot * tot || bt2 < S(1e-4) * tot || bn2 < S(1e-4) * tot;
+  }
+
+  // Wave speeds and Roe-Balsara normalization of one direction, in precision R.
+  template <class R>
+  __host__ __device__ static void eigenstructure(R rho, R p, R Bn, R By, R Bz, R gamma, R* out) {
+    const R irho = R(1) / rho;
+    const R a2 = gamma * p * irho;
+    const R bn2 = Bn * Bn * irho;
+    const R bt2r = By * By + Bz * Bz;
+    const R bt2 = bt2r * irho;
+    const R b2 = bn2 + bt2;
+    const R disc = sqrt(sq(a2 - bn2) + bt2 * (R(2) * a2 + R(2) * bn2 + bt2));
+    const R cf2 = R(0.5) * (a2 + b2 + disc);
+    const R cs2 = cf2 > R(0) ? a2 * bn2 / cf2 : R(0);
+    R af, as, by, bz;
+    if (disc > R(0)) {
+      const R diff = a2 - b2;
+      const R nf = diff >= R(0) ? R(0.5) * (diff + disc) : R(2) * a2 * bt2 / (disc - diff);
+      const R ns = diff <= R(0) ? R(0.5) * (disc - diff) : R(2) * a2 * bt2 / (disc + diff);
+      af = sqrt(fmin(R(1), fmax(R(0), nf / disc)));
+      as = sqrt(fmin(R(1), fmax(R(0), ns / disc)));
+    } else {
+      af = R(1);
+      as = R(0);
+    }
+    if (bt2r > R(0)) {
+      const R ibt = R(1) / sqrt(bt2r);
+      by = By * ibt;
+      bz = Bz * ibt;
+    } else {
+      by = R(0.70710678118654752440);
+      bz = R(0.70710678118654752440);
+    }
+    out[0] = a2;
+    out[1] = sqrt(a2);
+    out[2] = sqrt(cf2);
+    out[3] = sqrt(cs2);
+    out[4] = sqrt(bn2);
+    out[5] = af;
+    out[6] = as;
+    out[7] = by;
+    out[8] = bz;
+  }
+
   __host__ __device__ static void split(int d, const S* Ug, const Phys& ph, S Lam, S ch, S* Fg, S* Dg) {
     const S gamma = S(ph.gamma);
     const S gm1 = gamma - S(1);
@@ -301,40 +357,28 @@ struct Cell<K_MHD, DIM, S> {
     F[6] = u * By - Bn * v;
     F[7] = u * Bz - Bn * w;
     F[8] = ch * ch * Bn;
-    // wave speeds and Roe-Balsara normalization
+    // wave speeds and Roe-Balsara normalization; in FP32 the directions whose
+    // speeds nearly coincide get this eigenstructure in FP64
     Waves W;
     W.rho = rho;
     W.sr = sqrt(rho);
-    W.a2 = gamma * p * irho;
-    W.a = sqrt(W.a2);
-    const S bn2 = Bn * Bn * irho;
-    const S bt2r = By * By + Bz * Bz;
-    const S bt2 = bt2r * irho;
-    const S b2 = bn2 + bt2;
-    const S disc = sqrt(sq(W.a2 - bn2) + bt2 * (S(2) * W.a2 + S(2) * bn2 + bt2));
-    const S cf2 = S(0.5) * (W.a2 + b2 + disc);
-    const S cs2 = cf2 > S(0) ? W.a2 * bn2 / cf2 : S(0);
-    W.cf = sqrt(cf2);
-    W.cs = sqrt(cs2);
-    const S ca = sqrt(bn2);
-    if (disc > S(0)) {
-      const S diff = W.a2 - b2;
-      const S nf = diff >= S(0) ? S(0.5) * (diff + disc) : S(2) * W.a2 * bt2 / (disc - diff);
-      const S ns = diff <= S(0) ? S(0.5) * (disc - diff) : S(2) * W.a2 * bt2 / (disc + diff);
-      W.af = sqrt(fmin(S(1), fmax(S(0), nf / disc)));
-      W.as = sqrt(fmin(S(1), fmax(S(0), ns / disc)));
+    S eg[9];
+    if (sizeof(S) == 4 && near_degenerate(d, Ug, gamma)) {
+      double e64[9];
+      eigenstructure<double>(double(rho), double(p), double(Bn), double(By), double(Bz), double(gamma), e64);
+      for (int i = 0; i < 9; ++i) eg[i] = S(e64[i]);
     } else {
-      W.af = S(1);
-      W.as = S(0);
+      eigenstructure<S>(rho, p, Bn, By, Bz, gamma, eg);
     }
-    if (bt2r > S(0)) {
-      const S ibt = S(1) / sqrt(bt2r);
-      W.by = By * ibt;
-      W.bz = Bz * ibt;
-    } else {
-      W.by = S(0.70710678118654752440);
-      W.bz = S(0.70710678118654752440);
-    }
+    W.a2 = eg[0];
+    W.a = eg[1];
+    W.cf = eg[2];
+    W.cs = eg[3];
+    const S ca = eg[4];
+    W.af = eg[5];
+    W.as = eg[6];
+    W.by = eg[7];
+    W.bz = eg[8];
     W.sgn = Bn >= S(0) ? S(1) : S(-1);
     // speeds (f-, a-, s-, e, s+, a+, f+)
     S lam[7] = {u - W.cf, u - ca, u - W.cs, u, u + W.cs, u + ca, u + W.cf};
@@ -360,9 +404,10 @@ struct Cell<K_MHD, DIM, S> {
     project(W, xF, cF);
     project(W, xC, cC);
     const S qp = S(0.5) * (psi + ch * Bn), qm = S(0.5) * (psi - ch * Bn);
+    const S bcp = beta_w(ch, hk, ph.kinf), bcm = beta_w(-ch, hk, ph.kinf);
     for (int j = 0; j < 7; ++j) {
       const S bj = beta_w(lam[j], hk, ph.kinf);
-      const S sj = beta_dd(lam[j], ch, hk, ph.kinf) * qp + beta_dd(lam[j], -ch, hk, ph.kinf) * qm;
+      const S sj = beta_dd(lam[j], bj, ch, bcp, hk, ph.kinf) * qp + beta_dd(lam[j], bj, -ch, bcm, hk, ph.kinf) * qm;
       cD[j] = bj * cF[j] + sj * cC[j];
     }
     S y[7];
@@ -376,7 +421,7 @@ struct Cell<K_MHD, DIM, S> {
     D[4] = y[4] / gm1 + S(0.5) * uu * y[0] + rho * (u * y[1] + v * y[2] + w * y[3]) + By * y[5] + Bz * y[6];
     D[6] = y[5];
     D[7] = y[6];
-    const S eta = beta_w(ch, hk, ph.kinf) * ch;
+    const S eta = bcp * ch;
     D[5] = eta * Bn;
     D[8] = eta * psi;
     // scatter from the local frame

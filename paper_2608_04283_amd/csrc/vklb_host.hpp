@@ -31,8 +31,24 @@ struct Layout {
   size_t state_off, stage_off, fa_off, fb_off, part_off, diag_off, total;
   long long stride;
   int p, Q;
+  int slots;  // stored slots of p planes per buffer: Q, or Q + 1 with the low part of U
   size_t elem;
 };
+
+// Stored basis (the kernels' BASIS) from vklb_options::basis: 0 all Q
+// populations, 1 moving populations + U, 2 as 1 with U compensated (FP32).
+// Default: FP64 populations; FP32 compensated in 1D (runs there take tens of
+// thousands of steps and the launch, not HBM, bounds the step) and delta in 2D.
+// -1: not a valid choice.
+inline int resolve_basis(int opt, vklb_precision prec, int dim) {
+  switch (opt) {
+    case 0: return prec == VKLB_FP32 ? (dim == 1 ? 2 : 1) : 0;
+    case 1: return 0;
+    case 2: return 1;
+    case 3: return prec == VKLB_FP32 ? 2 : -1;
+  }
+  return -1;
+}
 
 constexpr int kDiagBlocks = 512;
 
@@ -42,7 +58,9 @@ inline long long max_step_blocks(const vklb_grid* g) {
   return ((g->n[0] + 63) / 64) * g->n[1];
 }
 
-inline bool layout_of(const vklb_system* sys, vklb_lattice lat, const vklb_grid* g, vklb_precision prec, Layout* L) {
+// basis: as resolve_basis returns it (sizes the population buffers).
+inline bool layout_of(const vklb_system* sys, vklb_lattice lat, const vklb_grid* g, vklb_precision prec, int basis,
+                      Layout* L) {
   if (!sys || !g) return false;
   if (g->dim != 1 && g->dim != 2) return false;
   if ((lat == VKLB_D1Q3) != (g->dim == 1)) return false;
@@ -54,25 +72,31 @@ inline bool layout_of(const vklb_system* sys, vklb_lattice lat, const vklb_grid*
   if (cells > (1ll << 31) - 1) return false;
   L->p = p;
   L->Q = g->dim == 1 ? 3 : 5;
+  L->slots = L->Q + (basis == 2 ? 1 : 0);
   L->elem = prec == VKLB_FP32 ? 4 : 8;
   L->stride = (cells + 63) / 64 * 64;
   const size_t plane = size_t(L->stride) * L->elem;
   L->state_off = 0;
   L->stage_off = align_up(sizeof(DevState));
   L->fa_off = align_up(L->stage_off + size_t(p) * cells * 8);
-  L->fb_off = align_up(L->fa_off + size_t(L->Q) * p * plane);
-  L->part_off = align_up(L->fb_off + size_t(L->Q) * p * plane);
+  L->fb_off = align_up(L->fa_off + size_t(L->slots) * p * plane);
+  L->part_off = align_up(L->fb_off + size_t(L->slots) * p * plane);
   L->diag_off = align_up(L->part_off + size_t(2) * 2 * max_step_blocks(g) * 8);
   L->total = align_up(L->diag_off + size_t(kDiagBlocks) * 9 * 2 * 8 + 256);
   return true;
 }
 
 
-inline int default_width(long long nx) { return nx <= 64 ? 64 : (nx <= 128 ? 128 : 256); }
+// 2D: strip width; 1D: workgroup size (512 once 256-lane tiles would need
+// more workgroups than the 256 compute units).
+inline int default_width(int dim, long long nx) {
+  if (dim == 1) return (nx + 253) / 254 > 256 ? 512 : 256;
+  return nx <= 64 ? 64 : (nx <= 128 ? 128 : 256);
+}
 inline int default_band(int kind) { return kind == VKLB_MHD_GLM ? 16 : 32; }
 
 inline int step_grid_of(const vklb_grid* g, int width, int band) {
-  if (g->dim == 1) return int((g->n[0] + 253) / 254);
+  if (g->dim == 1) return int((g->n[0] + width - 3) / (width - 2));
   return int(((g->n[0] + width - 1) / width) * ((g->n[1] + band - 1) / band));
 }
 
@@ -112,7 +136,7 @@ inline vklb_status validate(const vklb_system* sys, vklb_lattice lat, const vklb
     return bad(VKLB_ERR_ARG, "gamma must be > 1");
   if (sys->kind == VKLB_MHD_GLM && !(sys->ch_factor > 0.0)) return bad(VKLB_ERR_ARG, "ch_factor must be > 0");
   Layout L;
-  if (!layout_of(sys, lat, grid, prec, &L)) return bad(VKLB_ERR_UNSUPPORTED, "grid too large or invalid");
+  if (!layout_of(sys, lat, grid, prec, 0, &L)) return bad(VKLB_ERR_UNSUPPORTED, "grid too large or invalid");
   return VKLB_OK;
 }
 
@@ -151,12 +175,12 @@ inline SolveDesc make_desc(char* base, const Layout& L, const vklb_system* sys, 
   return d;
 }
 
-inline Launchers pick_launchers(int kind, int dim, int prec, int delta, int width) {
+inline Launchers pick_launchers(int kind, int dim, int prec, int basis, int width) {
   switch (kind) {
-    case VKLB_SHALLOW_WATER: return launchers_sw(dim, prec, delta, width);
-    case VKLB_EULER: return launchers_euler(dim, prec, delta, width);
-    case VKLB_MHD_GLM: return launchers_mhd(dim, prec, delta, width);
-    default: return launchers_linear(dim, prec, delta, width);
+    case VKLB_SHALLOW_WATER: return launchers_sw(dim, prec, basis, width);
+    case VKLB_EULER: return launchers_euler(dim, prec, basis, width);
+    case VKLB_MHD_GLM: return launchers_mhd(dim, prec, basis, width);
+    default: return launchers_linear(dim, prec, basis, width);
   }
 }
 

@@ -197,27 +197,58 @@ __device__ inline void carry_done(const SolveDesc& sd, const Step& S, int tile) 
   }
 }
 
-// Split arithmetic type: the MHD eigen-split always runs in FP64.
+// Split arithmetic type (the FP32 MHD split switches to FP64 per direction
+// near coinciding speeds, inside Cell<K_MHD, DIM, float>::split).
 template <int KIND, class T> struct SplitType { using type = T; };
-template <class T> struct SplitType<K_MHD, T> { using type = double; };
 
-template <int KIND, int DIM, class T, bool DELTA>
+// Stored bases of a cell (BASIS): 0 the Q populations; 1 the moving
+// populations and U in the rest slot ("delta": U^{n+1} = U^n plus the
+// differences of the moving populations, which keeps the small per-step
+// increment out of a large FP32 sum); 2 as 1 with U kept as an unevaluated
+// FP32 pair hi + lo, lo in an extra slot Q (compensated update), so the
+// rounding of U does not accumulate over many steps.
+template <int KIND, int DIM, class T, int BASIS>
 struct Kern {
   static constexpr int P = SysInfo<KIND, DIM>::P;
   static constexpr int Q = DIM == 1 ? 3 : 5;
   static constexpr int REST = DIM == 1 ? 1 : 2;
+  static constexpr bool DELTA = BASIS >= 1;
+  static constexpr bool COMP = BASIS == 2;
   using ST = typename SplitType<KIND, T>::type;
 
-  // Load a cell, form U^n and the post-collision populations
-  // f* = f - omega (f - f^eq(U^n)) (Sec. 3.5 collision). In the delta basis
-  // U is loaded and the rest population is not formed.
-  __device__ static inline void collide(const T* __restrict__ src, long long stride, int cell, const Phys& ph,
-                                        double ixi, double Lam, double ch, T (&fs)[Q][P], T (&U)[P]) {
-    T f[Q][P];
+  __device__ static inline void load(const T* __restrict__ src, long long stride, int cell, T (&f)[Q][P]) {
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
       for (int v = 0; v < P; ++v) f[q][v] = src[(long long)(q * P + v) * stride + cell];
+  }
+
+  // Low part of U (compensated basis only).
+  __device__ static inline void load_lo(const T* __restrict__ src, long long stride, int cell, T (&lo)[P]) {
+#pragma unroll
+    for (int v = 0; v < P; ++v) lo[v] = COMP ? src[(long long)(Q * P + v) * stride + cell] : T(0);
+  }
+
+  // U^{n+1} = U^n + d in the delta bases; the compensated one adds d and the
+  // carried low part to hi with an error-free sum (Knuth's TwoSum), keeping
+  // the rounding error as the new low part.
+  __device__ static inline T advance(T hi, T d, T lo, T& lo_new) {
+    if (!COMP) {
+      lo_new = T(0);
+      return hi + d;
+    }
+    const T b = d + lo;
+    const T s = hi + b;
+    const T bb = s - hi;
+    lo_new = (hi - (s - bb)) + (b - bb);
+    return s;
+  }
+
+  // From a cell's stored values form U^n and the post-collision populations
+  // f* = f - omega (f - f^eq(U^n)) (Sec. 3.5 collision). In the delta basis U
+  // is stored and the rest population is not formed.
+  __device__ static inline void relax(const T (&f)[Q][P], const Phys& ph, double ixi, double Lam, double ch,
+                                      T (&fs)[Q][P], T (&U)[P]) {
 #pragma unroll
     for (int v = 0; v < P; ++v) {
       if (DELTA) {
@@ -243,6 +274,13 @@ struct Kern {
     }
   }
 
+  __device__ static inline void collide(const T* __restrict__ src, long long stride, int cell, const Phys& ph,
+                                        double ixi, double Lam, double ch, T (&fs)[Q][P], T (&U)[P]) {
+    T f[Q][P];
+    load(src, stride, cell, f);
+    relax(f, ph, ixi, Lam, ch, fs, U);
+  }
+
   // Speeds of a finished cell for the global maxima; flags non-physical states.
   __device__ static inline void new_state(const SolveDesc& sd, const T (&U)[P], long long cell, long long step,
                                           double& lam, double& cfm) {
@@ -265,36 +303,44 @@ struct Kern {
 // 1D step: workgroups of 256 lanes own 254 consecutive output cells plus one
 // halo cell on each side whose collision they recompute.
 // ---------------------------------------------------------------------------
-template <int KIND, class T, bool DELTA>
+// 1D step: workgroups of B lanes own B - 2 consecutive output cells plus one
+// halo cell on each side whose collision they recompute. The cell's stored
+// values are loaded before the partials of the previous launch are reduced,
+// so the two memory latencies overlap.
+template <int KIND, class T, int BASIS, int B>
 __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
-  using K = Kern<KIND, 1, T, DELTA>;
-  constexpr int P = K::P, Q = 3;
-  __shared__ double red[10];
+  using K = Kern<KIND, 1, T, BASIS>;
+  constexpr bool DELTA = K::DELTA;
+  constexpr int P = K::P, Q = 3, TW = B - 2;
+  __shared__ double red[2 * (B / 64) + 2];
+  const int N = sd.nx;
+  const int tid = threadIdx.x;
+  const int x = tile * TW - 1 + tid;
+  const int xl = map_index(x < N + 1 ? x : N, N, sd.bcx);
+  const long long stride = sd.stride;
+  const long long n0 = sd.st->S[sd.par].n;
+  T f[Q][P], lo[P];
+  K::load((const T*)((n0 & 1) ? sd.fb : sd.fa), stride, xl, f);
+  K::load_lo((const T*)((n0 & 1) ? sd.fb : sd.fa), stride, xl, lo);
   const Step S = begin_step(sd, red);
   if (S.done) {
     carry_done(sd, S, tile);
     return;
   }
   const long long n = S.n;
-  const T* __restrict__ src = (const T*)((n & 1) ? sd.fb : sd.fa);
   T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
   const double ixi = 1.0 / S.xi, Lam = S.lam, ch = S.ch;
-  const int N = sd.nx;
-  const int tid = threadIdx.x;
-  const int x = tile * 254 - 1 + tid;
-  const int xl = map_index(x < N + 1 ? x : N, N, sd.bcx);
-  const long long stride = sd.stride;
 
-  __shared__ T s_plus[P][256], s_minus[P][256];
+  __shared__ T s_plus[P][B], s_minus[P][B];
 
   T fs[Q][P], U[P];
-  K::collide(src, stride, xl, sd.ph, ixi, Lam, ch, fs, U);
+  K::relax(f, sd.ph, ixi, Lam, ch, fs, U);
 #pragma unroll
   for (int v = 0; v < P; ++v) { s_plus[v][tid] = fs[0][v]; s_minus[v][tid] = fs[2][v]; }
   __syncthreads();
 
   double lam = 0.0, cfm = 0.0;
-  if (tid >= 1 && tid <= 254 && x < N) {
+  if (tid >= 1 && tid <= TW && x < N) {
     T Un[P];
 #pragma unroll
     for (int v = 0; v < P; ++v) {
@@ -303,8 +349,10 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
       dst[(long long)(0 * P + v) * stride + x] = a;
       dst[(long long)(2 * P + v) * stride + x] = b;
       if (DELTA) {
-        Un[v] = U[v] + ((a - fs[0][v]) + (b - fs[2][v]));
+        T lo_new;
+        Un[v] = K::advance(U[v], (a - fs[0][v]) + (b - fs[2][v]), lo[v], lo_new);
         dst[(long long)(1 * P + v) * stride + x] = Un[v];
+        if (K::COMP) dst[(long long)(Q * P + v) * stride + x] = lo_new;
       } else {
         dst[(long long)(1 * P + v) * stride + x] = fs[1][v];
         Un[v] = ((T(0) + a) + fs[1][v]) + b;
@@ -316,9 +364,9 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
   end_step(sd, S, tile, lam, cfm);
 }
 
-template <int KIND, class T, bool DELTA>
-__global__ void __launch_bounds__(256) k_step1d(const SolveDesc sd) {
-  step1d_tile<KIND, T, DELTA>(sd, blockIdx.x);
+template <int KIND, class T, int BASIS, int B>
+__global__ void __launch_bounds__(B) k_step1d(const SolveDesc sd) {
+  step1d_tile<KIND, T, BASIS, B>(sd, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -330,28 +378,35 @@ __global__ void __launch_bounds__(256) k_step1d(const SolveDesc sd) {
 // by wave 0 in batches of 32 rows; the rows below and above the band are
 // collided by the whole workgroup (only their y-moving populations are used).
 // ---------------------------------------------------------------------------
-template <int KIND, class T, bool DELTA, int W>
+template <int KIND, class T, int BASIS, int W>
 __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
-  using K = Kern<KIND, 2, T, DELTA>;
+  using K = Kern<KIND, 2, T, BASIS>;
+  constexpr bool DELTA = K::DELTA;
   constexpr int P = K::P, Q = 5, REST = 2;
   __shared__ double red[2 * (W / 64) + 2];
-  const Step S = begin_step(sd, red);
-  if (S.done) {
-    carry_done(sd, S, tile);
-    return;
-  }
-  const long long n = S.n;
-  const T* __restrict__ src = (const T*)((n & 1) ? sd.fb : sd.fa);
-  T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
-  const double ixi = 1.0 / S.xi, Lam = S.lam, ch = S.ch;
   const int nx = sd.nx, ny = sd.ny, H = sd.band;
-  const long long stride = sd.stride;
   const int nsx = (nx + W - 1) / W;
   const int sx = tile % nsx, sy = tile / nsx;
   const int x0 = sx * W, y0 = sy * H, y1 = min(y0 + H, ny);
   const int tid = threadIdx.x;
   const int x = x0 + tid;
   const int xl = map_index(x < nx + 1 ? x : nx, nx, sd.bcx);
+  const long long stride = sd.stride;
+  const long long n0 = sd.st->S[sd.par].n;
+  const T* __restrict__ src = (const T*)((n0 & 1) ? sd.fb : sd.fa);
+  // stored values of row y0 - 1 (only its +y population is used) and of row y0
+  T fbelow[Q][P], fraw[Q][P], lo[P];
+  K::load(src, stride, map_index(y0 - 1, ny, sd.bcy) * nx + xl, fbelow);
+  K::load(src, stride, y0 * nx + xl, fraw);
+  K::load_lo(src, stride, y0 * nx + xl, lo);
+  const Step S = begin_step(sd, red);
+  if (S.done) {
+    carry_done(sd, S, tile);
+    return;
+  }
+  const long long n = S.n;
+  T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
+  const double ixi = 1.0 / S.xi, Lam = S.lam, ch = S.ch;
 
   __shared__ T s_ex[3][2][P][W];      // row slot, (+x, -x), var, lane
   __shared__ T s_halo[2][2][32][P];   // batch buffer, (left +x, right -x), row, var
@@ -359,14 +414,11 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   T fs[Q][P], U[P];
   // Row y0 - 1: only its +y population is used (streams into row y0).
   T prev4[P];
-  {
-    const int yl = map_index(y0 - 1, ny, sd.bcy);
-    K::collide(src, stride, yl * nx + xl, sd.ph, ixi, Lam, ch, fs, U);
+  K::relax(fbelow, sd.ph, ixi, Lam, ch, fs, U);
 #pragma unroll
-    for (int v = 0; v < P; ++v) prev4[v] = fs[3][v];
-  }
+  for (int v = 0; v < P; ++v) prev4[v] = fs[3][v];
   // Values of row r-1 carried into iteration r.
-  T c_rest[P], c4[P], c5[P];
+  T c_rest[P], c4[P], c5[P], c_lo[P];
   double lam = 0.0, cfm = 0.0;
   for (int r = y0; r <= y1; ++r) {
     // halo columns for rows [r, r + 32) of the band
@@ -382,11 +434,14 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
         for (int v = 0; v < P; ++v) s_halo[buf][side][tid & 31][v] = side == 0 ? hf[0][v] : hf[1][v];
       }
     }
-    // collide row r (r == y1 is the row above the band: only its -y population is used)
-    {
-      const int yl = r < y1 ? r : map_index(y1, ny, sd.bcy);
-      K::collide(src, stride, yl * nx + xl, sd.ph, ixi, Lam, ch, fs, U);
+    // collide row r (r == y1 is the row above the band: only its -y population
+    // is used); row y0 was loaded before the partials reduction
+    if (r > y0) {
+      const int yr = r < y1 ? r : map_index(y1, ny, sd.bcy);
+      K::load(src, stride, yr * nx + xl, fraw);
+      if (K::COMP && r < y1) K::load_lo(src, stride, yr * nx + xl, lo);
     }
+    K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
     const int slot = r % 3;
     if (r < y1) {
 #pragma unroll
@@ -412,7 +467,9 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
         dst[(long long)(4 * P + v) * stride + cell] = a5;
         if (DELTA) {
           const T b1 = s_ex[ps][0][v][tid], b2 = s_ex[ps][1][v][tid];
-          Un[v] = c_rest[v] + (((a1 - b1) + (a2 - b2)) + ((a4 - c4[v]) + (a5 - c5[v])));
+          T lo_new;
+          Un[v] = K::advance(c_rest[v], ((a1 - b1) + (a2 - b2)) + ((a4 - c4[v]) + (a5 - c5[v])), c_lo[v], lo_new);
+          if (K::COMP) dst[(long long)(Q * P + v) * stride + cell] = lo_new;
         } else {
           Un[v] = ((((T(0) + a1) + a2) + c_rest[v]) + a4) + a5;
         }
@@ -427,6 +484,7 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
 #pragma unroll
     for (int v = 0; v < P; ++v) {
       c_rest[v] = DELTA ? U[v] : fs[REST][v];
+      c_lo[v] = lo[v];
       c4[v] = fs[3][v];
       c5[v] = fs[4][v];
     }
@@ -435,9 +493,9 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   end_step(sd, S, tile, lam, cfm);
 }
 
-template <int KIND, class T, bool DELTA, int W>
+template <int KIND, class T, int BASIS, int W>
 __global__ void __launch_bounds__(W) k_step2d(const SolveDesc sd) {
-  step2d_tile<KIND, T, DELTA, W>(sd, xcd_remap(blockIdx.x, gridDim.x));
+  step2d_tile<KIND, T, BASIS, W>(sd, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -451,7 +509,7 @@ struct WorkItem {
   int tile;
 };
 
-template <int KIND, int DIM, class T, bool DELTA, int W>
+template <int KIND, int DIM, class T, int BASIS, int W>
 __global__ void __launch_bounds__(W) k_step_batched(const SolveDesc* __restrict__ descs,
                                                     const WorkItem* __restrict__ work, const int* __restrict__ nwork,
                                                     int par) {
@@ -460,8 +518,8 @@ __global__ void __launch_bounds__(W) k_step_batched(const SolveDesc* __restrict_
   const WorkItem w = work[i];
   SolveDesc sd = descs[w.slot];
   sd.par = par;
-  if constexpr (DIM == 1) step1d_tile<KIND, T, DELTA>(sd, w.tile);
-  else step2d_tile<KIND, T, DELTA, W>(sd, w.tile);
+  if constexpr (DIM == 1) step1d_tile<KIND, T, BASIS, 256>(sd, w.tile);
+  else step2d_tile<KIND, T, BASIS, W>(sd, w.tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -497,9 +555,10 @@ __global__ void __launch_bounds__(256) k_init_reduce(const SolveDesc sd) {
   }
 }
 
-template <int KIND, int DIM, class T, bool DELTA>
+template <int KIND, int DIM, class T, int BASIS>
 __global__ void __launch_bounds__(256) k_init_feq(const SolveDesc sd) {
-  using K = Kern<KIND, DIM, T, DELTA>;
+  using K = Kern<KIND, DIM, T, BASIS>;
+  constexpr bool DELTA = K::DELTA;
   constexpr int P = K::P, Q = K::Q;
   using ST = typename K::ST;
   __shared__ double red[10];
@@ -519,13 +578,19 @@ __global__ void __launch_bounds__(256) k_init_feq(const SolveDesc sd) {
 #pragma unroll
       for (int v = 0; v < P; ++v)
         f[(long long)(q * P + v) * sd.stride + c] = (DELTA && q == K::REST) ? U[v] : T(fe[q][v]);
+    if (K::COMP) {
+#pragma unroll
+      for (int v = 0; v < P; ++v)
+        f[(long long)(Q * P + v) * sd.stride + c] = T(sd.stage[v * cells + c] - double(U[v]));
+    }
   }
 }
 
-// U = sum_q f_q (or the stored U in the delta basis) into the FP64 staging.
-template <int KIND, int DIM, class T, bool DELTA>
+// U = sum_q f_q (or the stored U, hi + lo when compensated) into the FP64 staging.
+template <int KIND, int DIM, class T, int BASIS>
 __global__ void __launch_bounds__(256) k_moments(const SolveDesc sd) {
-  using K = Kern<KIND, DIM, T, DELTA>;
+  using K = Kern<KIND, DIM, T, BASIS>;
+  constexpr bool DELTA = K::DELTA;
   constexpr int P = K::P, Q = K::Q;
   const long long n = sd.st->S[sd.par].n;
   const T* __restrict__ f = (const T*)((n & 1) ? sd.fb : sd.fa);
@@ -542,7 +607,7 @@ __global__ void __launch_bounds__(256) k_moments(const SolveDesc sd) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) s += f[(long long)(q * P + v) * sd.stride + c];
       }
-      out[v * cells + c] = double(s);
+      out[v * cells + c] = K::COMP ? double(s) + double(f[(long long)(Q * P + v) * sd.stride + c]) : double(s);
     }
   }
 }

@@ -20,10 +20,11 @@ struct Launchers {
   int block = 256;  // threads per step workgroup
 };
 
-// prec: 0 FP64, 1 FP32; delta: 0/1; width: 2D strip width (64/128/256).
-Launchers launchers_sw(int dim, int prec, int delta, int width);
-Launchers launchers_euler(int dim, int prec, int delta, int width);
-Launchers launchers_mhd(int dim, int prec, int delta, int width);
-Launchers launchers_linear(int dim, int prec, int delta, int width);
+// prec: 0 FP64, 1 FP32; basis: 0 populations, 1 delta, 2 compensated delta
+// (FP32 only); width: 1D workgroup size (256/512), 2D strip width (64/128/256).
+Launchers launchers_sw(int dim, int prec, int basis, int width);
+Launchers launchers_euler(int dim, int prec, int basis, int width);
+Launchers launchers_mhd(int dim, int prec, int basis, int width);
+Launchers launchers_linear(int dim, int prec, int basis, int width);
 
 }  // namespace vklb

@@ -144,7 +144,7 @@ struct vklb_pool {
   size_t budget = 0;
   Arena arena;
   vklb_precision prec = VKLB_FP32;
-  int delta = 1;
+  int basis[3] = {0, 0, 0};  // stored basis per dimension (index 1, 2)
   hipStream_t stream = nullptr;
   int device = 0;
   uint64_t next_ticket = 1;
@@ -195,7 +195,7 @@ vklb_status admit(vklb_pool* p) {
     r->off = off;
     r->slot = slot;
     p->slots[slot] = r;
-    const int width = 128;
+    const int width = r->grid.dim == 1 ? 256 : 128;  // the batched kernels' tile widths
     r->sd = make_desc(p->base + off, r->L, &r->sys, &r->grid, &r->speed, r->omega, r->bc, &r->eq, width, r->band);
     // initialization into the parity of the next round
     const long long cells = (long long)r->sd.nx * r->sd.ny;
@@ -273,7 +273,8 @@ vklb_status vklb_pool_create(size_t hbm_budget, vklb_precision prec, void* hip_s
   if (hbm_budget < (1u << 20)) return VKLB_ERR_ARG;
   vklb_pool* p = new vklb_pool();
   p->prec = prec;
-  p->delta = prec == VKLB_FP32 ? 1 : 0;
+  p->basis[1] = resolve_basis(0, prec, 1);
+  p->basis[2] = resolve_basis(0, prec, 2);
   p->stream = reinterpret_cast<hipStream_t>(hip_stream);
   p->budget = hbm_budget / kAlign * kAlign;
   p->slots.assign(kMaxSlots, nullptr);
@@ -294,7 +295,8 @@ vklb_status vklb_pool_create(size_t hbm_budget, vklb_precision prec, void* hip_s
   p->arena.reset(p->budget);
   for (int kind = 0; kind < 4; ++kind)
     for (int dim = 1; dim <= 2; ++dim)
-      p->cls_launch[class_of(kind, dim)] = pick_launchers(kind, dim, prec == VKLB_FP32 ? 1 : 0, p->delta, 128);
+      p->cls_launch[class_of(kind, dim)] =
+          pick_launchers(kind, dim, prec == VKLB_FP32 ? 1 : 0, p->basis[dim], dim == 1 ? 256 : 128);
   p->stats.arena_bytes = p->budget;
   *out = p;
   return VKLB_OK;
@@ -320,7 +322,7 @@ vklb_status vklb_pool_submit(vklb_pool* p, const vklb_request* rq, uint64_t* tic
   r->eq = rq->eq;
   r->T = rq->T;
   r->max_steps = rq->max_steps < 0 ? (1ll << 62) : rq->max_steps;
-  layout_of(&r->sys, r->lat, &r->grid, p->prec, &r->L);
+  layout_of(&r->sys, r->lat, &r->grid, p->prec, p->basis[r->grid.dim], &r->L);
   if (align_up(r->L.total) > p->budget) {
     delete r;
     return pfail(p, VKLB_ERR_OOM, "request larger than the pool arena");

@@ -91,7 +91,7 @@ __global__ void k_divb(const double* __restrict__ U, int nx, int ny, double dx, 
 // Trailer of a checkpoint blob (see vklb_state_bytes).
 struct CkptTrailer {
   unsigned long long magic;
-  int kind, dim, prec, delta;
+  int kind, dim, prec, basis;
   long long nx, ny;
   double t, lam7, cfm, pad0;
   long long n;
@@ -128,7 +128,7 @@ struct vklb_solver {
   bool timed = false;
   std::string err;
   int device = 0;
-  int delta = 0;
+  int basis = 0;
   long long launches = 0;   // step launches since init (selects the parity)
 };
 
@@ -198,7 +198,7 @@ CkptTrailer make_trailer(const vklb_solver* s) {
   tr.kind = s->sys.kind;
   tr.dim = s->grid.dim;
   tr.prec = s->prec;
-  tr.delta = s->delta;
+  tr.basis = s->basis;
   tr.nx = s->grid.n[0];
   tr.ny = s->grid.dim == 2 ? s->grid.n[1] : 1;
   return tr;
@@ -252,7 +252,8 @@ extern "C" {
 
 size_t vklb_workspace_bytes(const vklb_system* sys, vklb_lattice lat, const vklb_grid* grid, vklb_precision prec) {
   Layout L;
-  return layout_of(sys, lat, grid, prec, &L) ? L.total : 0;
+  // the largest stored basis of the precision, so any basis fits
+  return layout_of(sys, lat, grid, prec, prec == VKLB_FP32 ? 2 : 0, &L) ? L.total : 0;
 }
 
 vklb_status vklb_create(const vklb_system* sys, vklb_lattice lat, const vklb_grid* grid, const vklb_speed* lambda,
@@ -264,8 +265,10 @@ vklb_status vklb_create(const vklb_system* sys, vklb_lattice lat, const vklb_gri
   std::string msg;
   vklb_status vst = validate(sys, lat, grid, lambda, omega, bc, eq, prec, &msg);
   if (vst != VKLB_OK) return fail(nullptr, vst, msg);
+  const int basis = resolve_basis(opt ? opt->basis : 0, prec, grid->dim);
+  if (basis < 0) return fail(nullptr, VKLB_ERR_ARG, "basis must be 0..3 (3, compensated, needs FP32)");
   Layout L;
-  layout_of(sys, lat, grid, prec, &L);
+  layout_of(sys, lat, grid, prec, basis, &L);
   if (device_buf && buf_bytes < L.total) return fail(nullptr, VKLB_ERR_OOM, "device buffer smaller than vklb_workspace_bytes");
   if (device_buf && (reinterpret_cast<uintptr_t>(device_buf) % kAlign) != 0)
     return fail(nullptr, VKLB_ERR_ARG, "device buffer must be 256-byte aligned");
@@ -302,11 +305,11 @@ vklb_status vklb_create(const vklb_system* sys, vklb_lattice lat, const vklb_gri
     }
     s->own_buf = true;
   }
-  const int delta = s->opt.basis == 0 ? (prec == VKLB_FP32 ? 1 : 0) : (s->opt.basis == 2 ? 1 : 0);
   int width = s->opt.strip_width;
-  if (width != 64 && width != 128 && width != 256) width = default_width(grid->n[0]);
-  s->K = pick_launchers(sys->kind, grid->dim, prec == VKLB_FP32 ? 1 : 0, delta, width);
-  s->delta = delta;
+  if (grid->dim == 1 ? (width != 256 && width != 512) : (width != 64 && width != 128 && width != 256))
+    width = default_width(grid->dim, grid->n[0]);
+  s->K = pick_launchers(sys->kind, grid->dim, prec == VKLB_FP32 ? 1 : 0, basis, width);
+  s->basis = basis;
   int band = s->opt.band_rows;
   if (band < 1) band = default_band(sys->kind);
   if (band > 4096) band = 4096;
@@ -474,7 +477,7 @@ vklb_status vklb_diagnostics(vklb_solver* s, vklb_diag* dg) {
 
 size_t vklb_state_bytes(const vklb_solver* s) {
   if (!s) return 0;
-  return size_t(s->L.Q) * s->L.p * size_t(s->L.stride) * s->L.elem + sizeof(CkptTrailer);
+  return size_t(s->L.slots) * s->L.p * size_t(s->L.stride) * s->L.elem + sizeof(CkptTrailer);
 }
 
 vklb_status vklb_get_state(vklb_solver* s, void* host, double* t, int64_t* steps) {
@@ -508,7 +511,7 @@ vklb_status vklb_set_state(vklb_solver* s, const void* host) {
   memcpy(&tr, static_cast<const char*>(host) + pop, sizeof tr);
   const CkptTrailer me = make_trailer(s);
   if (tr.magic != me.magic || tr.kind != me.kind || tr.dim != me.dim || tr.prec != me.prec ||
-      tr.delta != me.delta || tr.nx != me.nx || tr.ny != me.ny || tr.n < 0)
+      tr.basis != me.basis || tr.nx != me.nx || tr.ny != me.ny || tr.n < 0)
     return fail(s, VKLB_ERR_ARG, "checkpoint does not belong to a solver of this shape");
   char* dst = (tr.n & 1) ? static_cast<char*>(s->sd.fb) : static_cast<char*>(s->sd.fa);
   HIPCHK(s, hipMemcpyAsync(dst, host, pop, hipMemcpyHostToDevice, s->stream));

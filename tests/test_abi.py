@@ -41,7 +41,8 @@ def test_workspace_bytes(vk):
     pop = 3 * 3 * 65536
     # two population buffers + FP64 staging of U, plus small state/partials
     assert b64 >= 2 * pop * 8 + 3 * 65536 * 8 and b64 < 2 * pop * 8 + 3 * 65536 * 8 + (1 << 20)
-    assert b32 >= 2 * pop * 4 + 3 * 65536 * 8 and b32 < b64
+    # FP32 sizes for its largest basis: one more slot for the low part of U
+    assert b32 >= 2 * (pop + 3 * 65536) * 4 + 3 * 65536 * 8 and b32 < b64
     bad = I.sod(10).with_(dim=2)
     assert vk.workspace_bytes(bad.with_(n=(10, 0)), "fp64") == 0
 
@@ -74,6 +75,18 @@ def create(vk, P, precision="fp64", **over):
 def test_invalid_arguments_rejected(vk, over, needle):
     r, msg = create(vk, I.sod(100), **over)
     assert r == vk.ERR_ARG and needle in msg
+
+
+@pytest.mark.parametrize("prec,basis", [("fp64", 3), ("fp32", 4), ("fp64", -1)])
+def test_invalid_basis_rejected(vk, prec, basis):
+    """Basis is checked before any device call, so this runs without a GPU."""
+    P = I.sod(100)
+    sysd, lat, grid, speed, eq, bc = vk._structs(P)
+    opt = vk.Options(basis, 0, 0, 0)
+    h = ctypes.c_void_p()
+    r = vk.lib().vklb_create(ctypes.byref(sysd), lat, ctypes.byref(grid), ctypes.byref(speed), P.omega, bc,
+                             ctypes.byref(eq), vk.PRECISIONS[prec], ctypes.byref(opt), None, 0, None, ctypes.byref(h))
+    assert r == vk.ERR_ARG and "basis" in vk.lib().vklb_last_error(None).decode()
 
 
 def test_lattice_grid_mismatch_and_dx_dy(vk):

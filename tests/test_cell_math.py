@@ -140,3 +140,22 @@ def test_feq_and_speeds_match_oracle(oracle, cc, system, dim):
             assert abs(lam[0] - seven) < 1e-13 * seven
         else:
             assert abs(lam[0] - lam_o) < 1e-13 * lam_o
+
+
+@pytest.mark.parametrize("deg", [None, "bt0", "bt_small", "triple", "bx0"])
+def test_mhd_split_fp32_at_degenerate_states(oracle, cc, deg):
+    """The FP32 MHD split (FP64 only near coinciding speeds) stays within
+    1e-6 of the oracle at and near degenerate states."""
+    O = oracle
+    rng = np.random.default_rng(25)
+    for dim in (1, 2):
+        cf = cfg(O, "mhd", dim)
+        pr = prm(gamma=2.0)
+        for _ in range(25):
+            U = rand_state("mhd", dim, rng, degenerate=deg)
+            ch = ch_for(O, cf, U)
+            Lam = max(np.max(np.abs(O.eigenvalues(cf, d, U, ch))) for d in range(dim))
+            for d in range(dim):
+                Fpo, _ = O.split(cf, d, U, ch, lam=Lam)
+                F, D = cc_split(cc, 4, "mhd", dim, d, U, pr, Lam, ch)
+                assert np.max(np.abs((0.5 * F + D) - Fpo)) < 1e-6 * (np.max(np.abs(F)) + 1.0)

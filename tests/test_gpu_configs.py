@@ -1,0 +1,95 @@
+"""The benchmark configurations against the oracle.
+
+Full-length runs compare with the oracle results stored by
+tests/golden/make_oracle_goldens.py (written by the oracle alone), at the
+configurations' own sizes (1D) or the sizes their oracle comparison names
+(2D: 512^2 Euler, 256^2 Orszag-Tang). At the full 2D benchmark sizes (2048^2
+Euler, 1024^2 MHD) the first steps are compared element by element with an
+oracle run of the same steps, in the launch configuration the benchmark times.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2608_04283_amd import inputs as I
+from parity_util import rel_l1, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+CASES = [
+    # (golden name, problem factory, precision, tolerance on relative L1 per field)
+    ("sw1d_dambreak_d1q2_n1000", lambda: I.dam_break(1000, c=0.5, k=0.0), "fp64", 1e-12),
+    ("sw1d_dambreak_wu_n1000_100steps", lambda: I.dam_break(1000, max_steps=100), "fp64", 1e-12),
+    ("euler1d_sod_n65536", lambda: I.sod(65536), "fp64", 1e-12),
+    ("euler1d_sod_n65536", lambda: I.sod(65536), "fp32", 1e-4),
+    ("euler1d_wave_n256", lambda: I.smooth_wave(256), "fp64", 1e-12),
+    ("euler1d_wave_n1024", lambda: I.smooth_wave(1024), "fp64", 1e-12),
+    ("euler1d_wave_n4096", lambda: I.smooth_wave(4096), "fp64", 1e-12),
+    ("euler1d_wave_n4096", lambda: I.smooth_wave(4096), "fp32", 1e-4),
+    ("euler2d_quadrants_n512_s0", lambda: I.quadrants(512, seed=0, steps=2000), "fp32", 1e-4),
+    ("mhd2d_orszag_tang_n256", lambda: I.orszag_tang(256, steps=1000), "fp32", 1e-4),
+    ("mhd1d_briowu_n16384", lambda: I.brio_wu(16384), "fp32", 1e-4),
+]
+
+
+@pytest.mark.parametrize("name,factory,prec,tol", CASES, ids=[f"{c[0]}-{c[2]}" for c in CASES])
+def test_config_full_length(gpu, name, factory, prec, tol):
+    path = os.path.join(GOLDEN, f"oracle_{name}.npz")
+    if not os.path.exists(path):
+        pytest.fail(f"missing {path}: run tests/golden/make_oracle_goldens.py")
+    ref = np.load(path)
+    P = factory()
+    print(f"[config] {name} {prec} n={P.n}", flush=True)
+    s = gpu.Solver(P, precision=prec)
+    s.init()
+    U, t, n = s.run()
+    s.close()
+    if prec == "fp64":
+        assert n == int(ref["steps"])
+    else:
+        assert abs(n - int(ref["steps"])) <= 1
+    assert abs(t - float(ref["t"])) <= 1e-6 * max(1.0, float(ref["t"]))
+    err = rel_l1(U, ref["U"])
+    print(f"[config] {name} {prec} steps={n} rel_l1={np.array2string(err, precision=2)}", flush=True)
+    assert np.all(err <= tol), err
+
+
+@pytest.mark.parametrize("factory,steps", [(lambda: I.quadrants(2048, seed=0, steps=2000), 3),
+                                           (lambda: I.orszag_tang(1024, steps=1000), 2)],
+                         ids=["euler2d_quadrants_n2048", "mhd2d_orszag_tang_n1024"])
+def test_full_size_first_steps(gpu, oracle, factory, steps):
+    """At the benchmark sizes, in the benchmark's launch configuration."""
+    P = factory().with_(max_steps=steps)
+    s = gpu.Solver(P, precision="fp32")
+    s.init()
+    U, t, n = s.run()
+    s.close()
+    ref = run_oracle(oracle, P)
+    assert n == ref["steps"] == steps
+    err = rel_l1(U, ref["U"])
+    print(f"[full] {P.name} steps={n} rel_l1={np.array2string(err, precision=2)}", flush=True)
+    assert np.all(err <= 1e-5), err
+    # the FP32 path stays within FP32 rounding of the FP64 oracle cell by cell
+    # (fields that are zero, or nearly, are scaled by the largest field)
+    peak = np.abs(ref["U"]).max(axis=1, keepdims=True)
+    scale = np.maximum(peak, 1e-3 * peak.max())
+    assert np.max(np.abs(U - ref["U"]) / scale) < 1e-5
+
+
+def test_mhd2d_orszag_tang_diagnostics(gpu):
+    """Sec. 5.3 problem family at the configuration's size: totals conserved on
+    the periodic grid, max|div B| reported (0 initially)."""
+    P = I.orszag_tang(1024, steps=1000)
+    s = gpu.Solver(P, precision="fp32")
+    s.init()
+    d0 = s.diagnostics()
+    s.step(1000)
+    d1 = s.diagnostics()
+    s.close()
+    assert d0["max_div_b"] < 1e-9 and d1["steps"] == 1000
+    assert np.isfinite(d1["max_div_b"]) and d1["max_div_b"] > 0
+    scale = np.abs(P.U0).sum(axis=1) + 1e-3 * np.abs(P.U0).sum()
+    assert np.all(np.abs(d1["totals"] - d0["totals"]) / scale < 1e-5)

@@ -45,6 +45,9 @@ CASES = {
     "euler1d_sod_fp32": (lambda: I.sod(3000), "fp32", {}),
     "euler1d_sod_fp64_delta": (lambda: I.sod(3000), "fp64", {"basis": 2}),
     "euler1d_sod_fp32_plain": (lambda: I.sod(3000), "fp32", {"basis": 1}),
+    "euler1d_sod_fp32_delta": (lambda: I.sod(3000), "fp32", {"basis": 2}),
+    "euler1d_wave_fp32": (lambda: I.smooth_wave(700), "fp32", {}),
+    "sw1d_wu_100steps_fp32_delta": (lambda: I.dam_break(1000, max_steps=100), "fp32", {"basis": 2}),
     "euler1d_wave_fp64": (lambda: I.smooth_wave(700), "fp64", {}),
     "euler1d_sod_local_alpha_fp64": (lambda: I.sod(1500, alpha_norm="local"), "fp64", {}),
     "euler1d_sod_discontinuous_fp64": (lambda: I.sod(1500, c=0.0, k=math.inf, nu=0.5), "fp64", {}),
@@ -55,6 +58,7 @@ CASES = {
                                                           nu=0.5), "fp64", {}),
     "euler2d_quad_fp64": (lambda: I.quadrants(300, seed=0, steps=60), "fp64", {}),
     "euler2d_quad_fp32": (lambda: I.quadrants(300, seed=0, steps=60), "fp32", {}),
+    "euler2d_quad_fp32_compensated": (lambda: I.quadrants(300, seed=0, steps=60), "fp32", {"basis": 3}),
     "euler2d_rect_periodic_fp64": (lambda: rect_quadrants(300, 170, 3, 50, bc=("periodic", "periodic")), "fp64",
                                    {}),
     "euler2d_rect_mixed_bc_fp32": (lambda: rect_quadrants(300, 170, 4, 50, bc=("periodic", "zero_gradient")),
@@ -65,6 +69,7 @@ CASES = {
     "sw2d_riemann_fp64": (lambda: I.random_riemann("sw", 2, 130, seed=7, max_steps=80), "fp64", {}),
     "sw2d_riemann_fp32": (lambda: I.random_riemann("sw", 2, 130, seed=7, max_steps=80), "fp32", {}),
     "mhd2d_riemann_fp32": (lambda: I.random_riemann("mhd", 2, 100, seed=9, max_steps=60), "fp32", {}),
+    "mhd2d_ot_fp32_compensated": (lambda: I.orszag_tang(96, steps=60), "fp32", {"basis": 3}),
     "linear2d_omega17_fp64": (lambda: linear2d(70, 40, 1.7), "fp64", {}),
 }
 
@@ -92,14 +97,14 @@ def test_parity_with_oracle(gpu, oracle, name):
     assert np.all(err <= TOL[prec]), err
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_tile_shapes_give_identical_results(gpu, prec):
+@pytest.mark.parametrize("prec,basis", [("fp64", 0), ("fp32", 0), ("fp32", 3)])
+def test_tile_shapes_give_identical_results(gpu, prec, basis):
     """No cross-cell float reduction feeds back into the state, so every strip
     width and band height gives the same bits."""
     P = rect_quadrants(300, 170, 5, 30)
     outs = []
     for w, b in ((256, 32), (128, 8), (64, 64), (256, 17)):
-        s = gpu.Solver(P, precision=prec, strip_width=w, band_rows=b)
+        s = gpu.Solver(P, precision=prec, basis=basis, strip_width=w, band_rows=b)
         s.init()
         outs.append(s.run()[0])
         s.close()
@@ -150,27 +155,55 @@ def test_periodic_totals_conserved(gpu, prec):
     assert d0["max_div_b"] < 1e-10
 
 
-def test_checkpoint_resume_is_exact(gpu):
-    P = I.quadrants(200, seed=1, steps=0)
+def test_fp32_compensated_update_removes_drift(gpu, oracle):
+    """A smooth wave over ~8k steps: the increments of U per step are O(dt),
+    so rounding U to FP32 every step builds up an error that grows with the
+    step count; the compensated pair keeps U to about FP32 rounding of the
+    populations. The delta basis must be clearly worse, and the compensated
+    one far inside the FP32 tolerance."""
+    P = I.smooth_wave(1024)
+    ref = run_oracle(oracle, P)
+    err = {}
+    for basis in (2, 3):
+        s = gpu.Solver(P, precision="fp32", basis=basis)
+        s.init()
+        U, t, n = s.run()
+        s.close()
+        err[basis] = rel_l1(U, ref["U"]).max()
+    print(f"[drift] delta {err[2]:.2e} compensated {err[3]:.2e}", flush=True)
+    assert err[3] <= 1e-6 and err[2] >= 4 * err[3]
+
+
+@pytest.mark.parametrize("dim,basis", [(2, 0), (1, 0), (2, 3)])
+def test_checkpoint_resume_is_exact(gpu, dim, basis):
+    P = I.quadrants(200, seed=1, steps=0) if dim == 2 else I.sod(3000, T=math.inf)
     P = P.with_(max_steps=2**62)
-    a = gpu.Solver(P, precision="fp32")
+    a = gpu.Solver(P, precision="fp32", basis=basis)
     a.init()
     a.step(37)
     buf, t, n = a.get_state()
     a.step(25)
     Ua, ta, na = a.moments()
     a.close()
-    b = gpu.Solver(P, precision="fp32")
+    b = gpu.Solver(P, precision="fp32", basis=basis)
     b.set_state(buf)
     b.step(25)
     Ub, tb, nb = b.moments()
     b.close()
     assert na == nb == 62 and ta == tb
     assert np.array_equal(Ua, Ub)
-    c = gpu.Solver(P.with_(n=(201, 200), hi=(201 / 200, 1.0)), precision="fp32")
+    # a blob of another shape or basis is rejected
+    other = P.with_(n=(201, 200), hi=(201 / 200, 1.0)) if dim == 2 else P.with_(n=(3001,))
+    c = gpu.Solver(other, precision="fp32", basis=basis)
     with pytest.raises(gpu.VklbError):
         c.set_state(np.zeros(c.state_bytes(), dtype=np.uint8))
     c.close()
+    # the all-populations basis: same size as the 2D default (rejected by the
+    # blob's trailer), smaller than the compensated ones (rejected by size)
+    d = gpu.Solver(P, precision="fp32", basis=1)
+    with pytest.raises(gpu.VklbError):
+        d.set_state(buf)
+    d.close()
 
 
 def test_nonphysical_state_reported(gpu, oracle):
