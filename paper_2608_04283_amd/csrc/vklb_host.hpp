@@ -74,7 +74,7 @@ inline bool layout_of(const vklb_system* sys, vklb_lattice lat, const vklb_grid*
   L->Q = g->dim == 1 ? 3 : 5;
   L->slots = L->Q + (basis == 2 ? 1 : 0);
   L->elem = prec == VKLB_FP32 ? 4 : 8;
-  L->stride = (cells + 63) / 64 * 64;
+  L->stride = (cells + kBlock - 1) / kBlock * kBlock;  // whole storage blocks
   const size_t plane = size_t(L->stride) * L->elem;
   L->state_off = 0;
   L->stage_off = align_up(sizeof(DevState));
@@ -87,13 +87,15 @@ inline bool layout_of(const vklb_system* sys, vklb_lattice lat, const vklb_grid*
 }
 
 
-// 2D: strip width; 1D: workgroup size (512 once 256-lane tiles would need
-// more workgroups than the 256 compute units).
+// 2D: strip width; 1D: workgroup size (256 lanes measured faster than 512 at
+// every 1D benchmark size: more, smaller workgroups start sooner).
 inline int default_width(int dim, long long nx) {
-  if (dim == 1) return (nx + 253) / 254 > 256 ? 512 : 256;
+  if (dim == 1) return 256;
   return nx <= 64 ? 64 : (nx <= 128 ? 128 : 256);
 }
-inline int default_band(int kind) { return kind == VKLB_MHD_GLM ? 16 : 32; }
+// Rows per 2D band: MHD holds so many registers that only two workgroups fit a
+// compute unit, so it takes short bands to have enough of them.
+inline int default_band(int kind) { return kind == VKLB_MHD_GLM ? 8 : 32; }
 
 inline int step_grid_of(const vklb_grid* g, int width, int band) {
   if (g->dim == 1) return int((g->n[0] + width - 3) / (width - 2));

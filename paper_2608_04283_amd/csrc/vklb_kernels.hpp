@@ -1,8 +1,11 @@
 // Device kernels of the WU-VKLB step for gfx950 (one fused kernel per step).
 //
-// Data layout in HBM: populations as structure of arrays, plane (q, var) of
-// `stride` elements at offset (q * P + var) * stride; cell = j * nx + i.
-// Two population buffers ping-pong by step parity. In the "delta" basis the
+// Data layout in HBM: cell = j * nx + i; cells are grouped in blocks of 256
+// consecutive cells and each block stores its stored values plane after plane
+// (plane = slot * P + var, 256 values each): structure of arrays inside a
+// block, so every load and store of a wavefront is one contiguous 256-byte
+// (FP32) run and a workgroup row touches one region, not Q * P far-apart
+// streams. Two population buffers ping-pong by step parity. In the "delta" basis the
 // rest-population plane holds U instead (the rest population is U minus the
 // moving ones), which keeps FP32 rounding relative to the small per-step
 // change of U rather than to U itself.
@@ -43,6 +46,10 @@ struct DevState {
 };
 
 // Everything a kernel needs to know about one solve (passed by value).
+// Cells per storage block of the population buffers.
+constexpr int kBlockLog2 = 8;
+constexpr int kBlock = 1 << kBlockLog2;
+
 struct SolveDesc {
   void* fa;
   void* fb;
@@ -55,7 +62,7 @@ struct SolveDesc {
   double xi_fixed;
   int xi_mode;           // 0 CFL, 1 fixed
   int nx, ny;            // ny = 1 in 1D
-  long long stride;      // elements per population plane
+  long long stride;      // cells rounded up to whole 256-cell blocks
   int bcx, bcy;          // 0 periodic, 1 zero gradient
   int nblocks;           // workgroups per step launch (= number of partials)
   int band;              // 2D rows per band
@@ -214,19 +221,28 @@ struct Kern {
   static constexpr int REST = DIM == 1 ? 1 : 2;
   static constexpr bool DELTA = BASIS >= 1;
   static constexpr bool COMP = BASIS == 2;
+  static constexpr int PLANES = (Q + (COMP ? 1 : 0)) * P;  // stored values per cell
   using ST = typename SplitType<KIND, T>::type;
 
-  __device__ static inline void load(const T* __restrict__ src, long long stride, int cell, T (&f)[Q][P]) {
+  // Element index of stored plane `plane` (slot * P + variable) of `cell`:
+  // cells are grouped in blocks of kBlock consecutive cells, and a block holds
+  // all its planes one after another, so the rows a workgroup reads and
+  // writes are few contiguous regions rather than PLANES far-apart streams.
+  __device__ static inline long long pidx(int plane, long long cell) {
+    return ((cell >> kBlockLog2) * PLANES + plane) * kBlock + (cell & (kBlock - 1));
+  }
+
+  __device__ static inline void load(const T* __restrict__ src, long long cell, T (&f)[Q][P]) {
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
-      for (int v = 0; v < P; ++v) f[q][v] = src[(long long)(q * P + v) * stride + cell];
+      for (int v = 0; v < P; ++v) f[q][v] = src[pidx(q * P + v, cell)];
   }
 
   // Low part of U (compensated basis only).
-  __device__ static inline void load_lo(const T* __restrict__ src, long long stride, int cell, T (&lo)[P]) {
+  __device__ static inline void load_lo(const T* __restrict__ src, long long cell, T (&lo)[P]) {
 #pragma unroll
-    for (int v = 0; v < P; ++v) lo[v] = COMP ? src[(long long)(Q * P + v) * stride + cell] : T(0);
+    for (int v = 0; v < P; ++v) lo[v] = COMP ? src[pidx(Q * P + v, cell)] : T(0);
   }
 
   // U^{n+1} = U^n + d in the delta bases; the compensated one adds d and the
@@ -274,10 +290,10 @@ struct Kern {
     }
   }
 
-  __device__ static inline void collide(const T* __restrict__ src, long long stride, int cell, const Phys& ph,
+  __device__ static inline void collide(const T* __restrict__ src, long long cell, const Phys& ph,
                                         double ixi, double Lam, double ch, T (&fs)[Q][P], T (&U)[P]) {
     T f[Q][P];
-    load(src, stride, cell, f);
+    load(src, cell, f);
     relax(f, ph, ixi, Lam, ch, fs, U);
   }
 
@@ -317,11 +333,10 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
   const int tid = threadIdx.x;
   const int x = tile * TW - 1 + tid;
   const int xl = map_index(x < N + 1 ? x : N, N, sd.bcx);
-  const long long stride = sd.stride;
   const long long n0 = sd.st->S[sd.par].n;
   T f[Q][P], lo[P];
-  K::load((const T*)((n0 & 1) ? sd.fb : sd.fa), stride, xl, f);
-  K::load_lo((const T*)((n0 & 1) ? sd.fb : sd.fa), stride, xl, lo);
+  K::load((const T*)((n0 & 1) ? sd.fb : sd.fa), xl, f);
+  K::load_lo((const T*)((n0 & 1) ? sd.fb : sd.fa), xl, lo);
   const Step S = begin_step(sd, red);
   if (S.done) {
     carry_done(sd, S, tile);
@@ -346,15 +361,15 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
     for (int v = 0; v < P; ++v) {
       const T a = s_plus[v][tid - 1];
       const T b = s_minus[v][tid + 1];
-      dst[(long long)(0 * P + v) * stride + x] = a;
-      dst[(long long)(2 * P + v) * stride + x] = b;
+      dst[K::pidx(0 * P + v, x)] = a;
+      dst[K::pidx(2 * P + v, x)] = b;
       if (DELTA) {
         T lo_new;
         Un[v] = K::advance(U[v], (a - fs[0][v]) + (b - fs[2][v]), lo[v], lo_new);
-        dst[(long long)(1 * P + v) * stride + x] = Un[v];
-        if (K::COMP) dst[(long long)(Q * P + v) * stride + x] = lo_new;
+        dst[K::pidx(1 * P + v, x)] = Un[v];
+        if (K::COMP) dst[K::pidx(Q * P + v, x)] = lo_new;
       } else {
-        dst[(long long)(1 * P + v) * stride + x] = fs[1][v];
+        dst[K::pidx(1 * P + v, x)] = fs[1][v];
         Un[v] = ((T(0) + a) + fs[1][v]) + b;
       }
     }
@@ -391,14 +406,17 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   const int tid = threadIdx.x;
   const int x = x0 + tid;
   const int xl = map_index(x < nx + 1 ? x : nx, nx, sd.bcx);
-  const long long stride = sd.stride;
   const long long n0 = sd.st->S[sd.par].n;
   const T* __restrict__ src = (const T*)((n0 & 1) ? sd.fb : sd.fa);
   // stored values of row y0 - 1 (only its +y population is used) and of row y0
-  T fbelow[Q][P], fraw[Q][P], lo[P];
-  K::load(src, stride, map_index(y0 - 1, ny, sd.bcy) * nx + xl, fbelow);
-  K::load(src, stride, y0 * nx + xl, fraw);
-  K::load_lo(src, stride, y0 * nx + xl, lo);
+  // Systems with few values per cell (SW, Euler) load row r + 1 while row r
+  // is collided, so a row's memory latency overlaps the previous row's work;
+  // MHD has no registers to spare for it.
+  constexpr bool PREFETCH = Q * P <= 20;
+  T fbelow[Q][P], fraw[Q][P], lo[P], fnext[Q][P], lonext[P];
+  K::load(src, map_index(y0 - 1, ny, sd.bcy) * nx + xl, fbelow);
+  K::load(src, y0 * nx + xl, fraw);
+  K::load_lo(src, y0 * nx + xl, lo);
   const Step S = begin_step(sd, red);
   if (S.done) {
     carry_done(sd, S, tile);
@@ -429,17 +447,23 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
       if (row < y1) {
         const int hx = map_index(side == 0 ? x0 - 1 : x0 + W, nx, sd.bcx);
         T hf[Q][P], hU[P];
-        K::collide(src, stride, row * nx + hx, sd.ph, ixi, Lam, ch, hf, hU);
+        K::collide(src, row * nx + hx, sd.ph, ixi, Lam, ch, hf, hU);
 #pragma unroll
         for (int v = 0; v < P; ++v) s_halo[buf][side][tid & 31][v] = side == 0 ? hf[0][v] : hf[1][v];
       }
     }
     // collide row r (r == y1 is the row above the band: only its -y population
     // is used); row y0 was loaded before the partials reduction
-    if (r > y0) {
+    if (PREFETCH) {
+      if (r < y1) {
+        const int yn = r + 1 < y1 ? r + 1 : map_index(y1, ny, sd.bcy);
+        K::load(src, yn * nx + xl, fnext);
+        if (K::COMP && r + 1 < y1) K::load_lo(src, yn * nx + xl, lonext);
+      }
+    } else if (r > y0) {
       const int yr = r < y1 ? r : map_index(y1, ny, sd.bcy);
-      K::load(src, stride, yr * nx + xl, fraw);
-      if (K::COMP && r < y1) K::load_lo(src, stride, yr * nx + xl, lo);
+      K::load(src, yr * nx + xl, fraw);
+      if (K::COMP && r < y1) K::load_lo(src, yr * nx + xl, lo);
     }
     K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
     const int slot = r % 3;
@@ -461,19 +485,19 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
         const T a2 = tid < W - 1 ? s_ex[ps][1][v][tid + 1] : s_halo[hb][1][hr][v];
         const T a4 = prev4[v];
         const T a5 = fs[4][v];
-        dst[(long long)(0 * P + v) * stride + cell] = a1;
-        dst[(long long)(1 * P + v) * stride + cell] = a2;
-        dst[(long long)(3 * P + v) * stride + cell] = a4;
-        dst[(long long)(4 * P + v) * stride + cell] = a5;
+        dst[K::pidx(0 * P + v, cell)] = a1;
+        dst[K::pidx(1 * P + v, cell)] = a2;
+        dst[K::pidx(3 * P + v, cell)] = a4;
+        dst[K::pidx(4 * P + v, cell)] = a5;
         if (DELTA) {
           const T b1 = s_ex[ps][0][v][tid], b2 = s_ex[ps][1][v][tid];
           T lo_new;
           Un[v] = K::advance(c_rest[v], ((a1 - b1) + (a2 - b2)) + ((a4 - c4[v]) + (a5 - c5[v])), c_lo[v], lo_new);
-          if (K::COMP) dst[(long long)(Q * P + v) * stride + cell] = lo_new;
+          if (K::COMP) dst[K::pidx(Q * P + v, cell)] = lo_new;
         } else {
           Un[v] = ((((T(0) + a1) + a2) + c_rest[v]) + a4) + a5;
         }
-        dst[(long long)(REST * P + v) * stride + cell] = DELTA ? Un[v] : c_rest[v];
+        dst[K::pidx(REST * P + v, cell)] = DELTA ? Un[v] : c_rest[v];
       }
       K::new_state(sd, Un, cell, n + 1, lam, cfm);
     }
@@ -487,6 +511,16 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
       c_lo[v] = lo[v];
       c4[v] = fs[3][v];
       c5[v] = fs[4][v];
+    }
+    if (PREFETCH && r < y1) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int v = 0; v < P; ++v) fraw[q][v] = fnext[q][v];
+      if (K::COMP) {
+#pragma unroll
+        for (int v = 0; v < P; ++v) lo[v] = lonext[v];
+      }
     }
   }
   block_max2(lam, cfm, red);
@@ -577,11 +611,11 @@ __global__ void __launch_bounds__(256) k_init_feq(const SolveDesc sd) {
     for (int q = 0; q < Q; ++q)
 #pragma unroll
       for (int v = 0; v < P; ++v)
-        f[(long long)(q * P + v) * sd.stride + c] = (DELTA && q == K::REST) ? U[v] : T(fe[q][v]);
+        f[K::pidx(q * P + v, c)] = (DELTA && q == K::REST) ? U[v] : T(fe[q][v]);
     if (K::COMP) {
 #pragma unroll
       for (int v = 0; v < P; ++v)
-        f[(long long)(Q * P + v) * sd.stride + c] = T(sd.stage[v * cells + c] - double(U[v]));
+        f[K::pidx(Q * P + v, c)] = T(sd.stage[v * cells + c] - double(U[v]));
     }
   }
 }
@@ -601,13 +635,13 @@ __global__ void __launch_bounds__(256) k_moments(const SolveDesc sd) {
     for (int v = 0; v < P; ++v) {
       T s;
       if (DELTA) {
-        s = f[(long long)(K::REST * P + v) * sd.stride + c];
+        s = f[K::pidx(K::REST * P + v, c)];
       } else {
         s = T(0);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) s += f[(long long)(q * P + v) * sd.stride + c];
+        for (int q = 0; q < Q; ++q) s += f[K::pidx(q * P + v, c)];
       }
-      out[v * cells + c] = K::COMP ? double(s) + double(f[(long long)(Q * P + v) * sd.stride + c]) : double(s);
+      out[v * cells + c] = K::COMP ? double(s) + double(f[K::pidx(Q * P + v, c)]) : double(s);
     }
   }
 }
