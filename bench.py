@@ -121,6 +121,37 @@ def time_workload(name, prec, K, W, quick=False):
             "cells": cells, "t_end": t_end, "roofline": roof, "wall_s": wall, "dtype": "f32" if prec == "fp32" else "f64"}
 
 
+def serving_bench(count, seed=1, budget=None):
+    """Batched serving vs plain per-solve launches on a sample of the mixed
+    request stream (systems, sizes and step counts drawn as in
+    inputs.serving_requests). Capacity = solves/s of the batched pool with
+    every request present at once; the timed streams then arrive as a Poisson
+    process at 80 % of that capacity, once through the pool and once through
+    plain per-solve launches."""
+    import torch
+    from paper_2608_04283_amd import serving
+    if budget is None:
+        free, _ = torch.cuda.mem_get_info()
+        budget = int(min(free * 0.6, 96 << 30)) // 256 * 256
+    reqs = I.serving_requests(count, seed=seed)
+    cell_steps = sum(r.problem.cells * r.steps for r in reqs)
+    cap = serving.run_batched(reqs, budget, "fp32", realtime=False)
+    rate = 0.8 * cap["solves_per_s"]
+    timed = serving.with_arrivals(reqs, rate, seed=seed + 1)
+    batched = serving.run_batched(timed, budget, "fp32", realtime=True)
+    plain_cap = serving.run_plain(reqs, "fp32", realtime=False)
+    plain = serving.run_plain(timed, "fp32", realtime=True)
+    keep = ("solves", "makespan_s", "solves_per_s", "p50_s", "p99_s", "mcell_steps_per_s", "nonphysical", "failed")
+    r = lambda d: {k: (round(d[k], 4) if isinstance(d[k], float) else d[k]) for k in keep}
+    return {"requests": count, "seed": seed, "cell_steps": cell_steps, "arena_bytes": budget,
+            "capacity_solves_per_s": round(cap["solves_per_s"], 3),
+            "capacity_mcell_steps_per_s": round(cap["mcell_steps_per_s"], 1),
+            "arrival_rate_per_s": round(rate, 3),
+            "batched": r(batched), "plain": r(plain),
+            "plain_capacity_solves_per_s": round(plain_cap["solves_per_s"], 3),
+            "batched_over_plain_capacity": round(cap["solves_per_s"] / plain_cap["solves_per_s"], 3)}
+
+
 def cpu_baseline(name):
     from oracle import oracle as O
     factory, _, sample_steps = WORKLOADS[name]
@@ -147,6 +178,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-also", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-other-precision", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=200,
+                    help="requests in the serving sample (0: skip serving)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run three device-to-device copies of MIB MiB (a plain copy kernel of known size, "
+                         "for scaling the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X (no multi-GPU path)",
@@ -156,6 +192,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": 3}))
+        return
     _, precs, _ = WORKLOADS[args.workload]
     prec = args.precision or precs[0]
     main_res = time_workload(args.workload, prec, args.steps, args.warmup)
@@ -196,6 +241,8 @@ def main():
             also[name] = {"value": round(r["value"], 2), "dtype": r["dtype"], "ms_per_solve": round(r["ms_per_solve"], 3),
                           "steps_per_solve": r["steps_per_solve"], "roofline": r["roofline"]}
         out["also"] = also
+    if args.serving_requests > 0:
+        out["serving"] = serving_bench(args.serving_requests)
     print(json.dumps(out))
 
 

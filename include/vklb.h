@@ -111,7 +111,9 @@ typedef struct {
                        Other values: VKLB_ERR_ARG. */
   int band_rows;    /* 2D: rows per workgroup band (8..64); 0 = tuned default */
   int graph_chunk;  /* steps captured per HIP graph (0 = 64; < 0: plain launches) */
-  int strip_width;  /* 2D: columns per workgroup (64, 128 or 256); 0 = tuned default */
+  int strip_width;  /* 2D: columns per workgroup (64, 128 or 256); 1D: lanes per workgroup
+                       (256 or 512, each finishing W - 2 cells); 0 = tuned default */
+  int halo_rows;    /* 2D: rows of the two halo columns collided per batch (1..32); 0 = tuned default */
 } vklb_options;
 
 typedef struct vklb_solver vklb_solver;

@@ -481,6 +481,21 @@ struct Equilibrium {
       }
     }
   }
+
+  // 2D: the two equilibria moving along axis d (+d into fplus, -d into
+  // fminus), needing only that direction's split; the same expressions as
+  // eval, so the results are bitwise those of eval.
+  __host__ __device__ static void eval_axis(const S* U, const Phys& ph, S ixi, S Lam, S ch, int d, S* fplus,
+                                            S* fminus) {
+    const S c = S(ph.c);
+    S F[P], D[P];
+    C::split(d, U, ph, Lam, ch, F, D);
+    for (int v = 0; v < P; ++v) {
+      const S Fp = S(0.5) * F[v] + D[v], Fm = S(0.5) * F[v] - D[v];
+      fplus[v] = c * U[v] + Fp * ixi;
+      fminus[v] = c * U[v] - Fm * ixi;
+    }
+  }
 };
 
 }  // namespace vklb

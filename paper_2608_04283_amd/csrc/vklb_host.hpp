@@ -96,6 +96,8 @@ inline int default_width(int dim, long long nx) {
 // Rows per 2D band: MHD holds so many registers that only two workgroups fit a
 // compute unit, so it takes short bands to have enough of them.
 inline int default_band(int kind) { return kind == VKLB_MHD_GLM ? 8 : 32; }
+// Rows of halo columns per batch (1..32).
+inline int default_halo(int kind) { return kind == VKLB_MHD_GLM ? 8 : 4; }
 
 inline int step_grid_of(const vklb_grid* g, int width, int band) {
   if (g->dim == 1) return int((g->n[0] + width - 3) / (width - 2));
@@ -145,7 +147,7 @@ inline vklb_status validate(const vklb_system* sys, vklb_lattice lat, const vklb
 // Kernel descriptor of a solve whose workspace starts at `base`.
 inline SolveDesc make_desc(char* base, const Layout& L, const vklb_system* sys, const vklb_grid* grid,
                            const vklb_speed* lambda, double omega, const vklb_bc bc[2], const vklb_equilibrium* eq,
-                           int width, int band) {
+                           int width, int band, int halo) {
   SolveDesc d;
   memset(&d, 0, sizeof d);
   d.fa = base + L.fa_off;
@@ -173,6 +175,7 @@ inline SolveDesc make_desc(char* base, const Layout& L, const vklb_system* sys, 
   d.bcx = bc[0] == VKLB_BC_PERIODIC ? 0 : 1;
   d.bcy = (grid->dim == 2 ? bc[1] : bc[0]) == VKLB_BC_PERIODIC ? 0 : 1;
   d.band = band;
+  d.halo = halo;
   d.nblocks = step_grid_of(grid, width, band);
   return d;
 }

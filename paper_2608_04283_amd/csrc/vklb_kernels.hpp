@@ -67,7 +67,7 @@ struct SolveDesc {
   int nblocks;           // workgroups per step launch (= number of partials)
   int band;              // 2D rows per band
   int par;               // launch parity
-  int pad;
+  int halo;              // 2D rows of halo columns collided per batch (1..32)
 };
 
 // Values every workgroup derives at the start of a step.
@@ -290,6 +290,31 @@ struct Kern {
     }
   }
 
+  // Delta bases, 2D: load only U (rest slot) and population q of a cell.
+  __device__ static inline void load_one(const T* __restrict__ src, long long cell, int q, T (&Ur)[P],
+                                         T (&fq)[P]) {
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+      Ur[v] = src[pidx(REST * P + v, cell)];
+      fq[v] = src[pidx(q * P + v, cell)];
+    }
+  }
+
+  // Delta bases, 2D: post-collision population of velocity +AXIS (plus) or
+  // -AXIS from U and that population alone, with the split of that axis
+  // only; bitwise what relax gives for it.
+  template <int AXIS>
+  __device__ static inline void relax_one(const T (&Ur)[P], const T (&fq)[P], bool plus, const Phys& ph,
+                                          double ixi, double Lam, double ch, T (&out)[P]) {
+    ST Us[P], fp[P], fm[P];
+#pragma unroll
+    for (int v = 0; v < P; ++v) Us[v] = ST(Ur[v]);
+    Equilibrium<KIND, DIM, ST>::eval_axis(Us, ph, ST(ixi), ST(Lam), ST(ch), AXIS, fp, fm);
+    const T om = T(ph.omega);
+#pragma unroll
+    for (int v = 0; v < P; ++v) out[v] = fq[v] - om * (fq[v] - T(plus ? fp[v] : fm[v]));
+  }
+
   __device__ static inline void collide(const T* __restrict__ src, long long cell, const Phys& ph,
                                         double ixi, double Lam, double ch, T (&fs)[Q][P], T (&U)[P]) {
     T f[Q][P];
@@ -390,7 +415,7 @@ __global__ void __launch_bounds__(B) k_step1d(const SolveDesc sd) {
 // (triple buffered, one barrier per row) to the lanes on either side, and row
 // r-1 is finished with the +y population kept from row r-2 and the -y
 // population of row r. The columns left and right of the strip are collided
-// by wave 0 in batches of 32 rows; the rows below and above the band are
+// by wave 0 in batches of `halo` rows; the rows below and above the band are
 // collided by the whole workgroup (only their y-moving populations are used).
 // ---------------------------------------------------------------------------
 template <int KIND, class T, int BASIS, int W>
@@ -413,8 +438,13 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   // is collided, so a row's memory latency overlaps the previous row's work;
   // MHD has no registers to spare for it.
   constexpr bool PREFETCH = Q * P <= 20;
+  // In the delta bases the rows y0 - 1 and y1 and the halo columns, of which
+  // one population each is used, load only U and that population (SW and
+  // Euler; for MHD the extra code paths cost more registers than it saves).
+  constexpr bool PARTIAL = DELTA && PREFETCH;
   T fbelow[Q][P], fraw[Q][P], lo[P], fnext[Q][P], lonext[P];
-  K::load(src, map_index(y0 - 1, ny, sd.bcy) * nx + xl, fbelow);
+  if (PARTIAL) K::load_one(src, map_index(y0 - 1, ny, sd.bcy) * nx + xl, 3, fbelow[REST], fbelow[3]);
+  else K::load(src, map_index(y0 - 1, ny, sd.bcy) * nx + xl, fbelow);
   K::load(src, y0 * nx + xl, fraw);
   K::load_lo(src, y0 * nx + xl, lo);
   const Step S = begin_step(sd, red);
@@ -427,45 +457,72 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   const double ixi = 1.0 / S.xi, Lam = S.lam, ch = S.ch;
 
   __shared__ T s_ex[3][2][P][W];      // row slot, (+x, -x), var, lane
-  __shared__ T s_halo[2][2][32][P];   // batch buffer, (left +x, right -x), row, var
+  __shared__ T s_halo[3][2][32][P];   // batch buffer, (left +x, right -x), row, var
 
   T fs[Q][P], U[P];
   // Row y0 - 1: only its +y population is used (streams into row y0).
   T prev4[P];
-  K::relax(fbelow, sd.ph, ixi, Lam, ch, fs, U);
+  if (PARTIAL) {
+    K::template relax_one<1>(fbelow[REST], fbelow[3], true, sd.ph, ixi, Lam, ch, prev4);
+  } else {
+    K::relax(fbelow, sd.ph, ixi, Lam, ch, fs, U);
 #pragma unroll
-  for (int v = 0; v < P; ++v) prev4[v] = fs[3][v];
+    for (int v = 0; v < P; ++v) prev4[v] = fs[3][v];
+  }
   // Values of row r-1 carried into iteration r.
   T c_rest[P], c4[P], c5[P], c_lo[P];
   double lam = 0.0, cfm = 0.0;
+  // The halo columns are collided by wave 0 in batches of hb rows (lanes
+  // 0..hb-1 left, 32..32+hb-1 right), hb rows ahead of the strip: a short
+  // batch reads them close in time to the neighbouring strips' own reads of
+  // the same cells, so those come from L2. Three batch buffers keep a batch
+  // from being overwritten while a slower wave still reads it.
+  const int hb = sd.halo;
   for (int r = y0; r <= y1; ++r) {
-    // halo columns for rows [r, r + 32) of the band
-    if (r < y1 && ((r - y0) & 31) == 0 && tid < 64) {
-      const int buf = ((r - y0) >> 5) & 1;
+    const int bq = (r - y0) / hb;
+    if (r < y1 && r - y0 == bq * hb && tid < 64) {
+      const int buf = bq % 3;
       const int side = tid >> 5;
       const int row = r + (tid & 31);
-      if (row < y1) {
+      if ((tid & 31) < hb && row < y1) {
         const int hx = map_index(side == 0 ? x0 - 1 : x0 + W, nx, sd.bcx);
-        T hf[Q][P], hU[P];
-        K::collide(src, row * nx + hx, sd.ph, ixi, Lam, ch, hf, hU);
+        if (PARTIAL) {
+          T hU[P], hq[P], hs[P];
+          K::load_one(src, row * nx + hx, side, hU, hq);
+          K::template relax_one<0>(hU, hq, side == 0, sd.ph, ixi, Lam, ch, hs);
 #pragma unroll
-        for (int v = 0; v < P; ++v) s_halo[buf][side][tid & 31][v] = side == 0 ? hf[0][v] : hf[1][v];
+          for (int v = 0; v < P; ++v) s_halo[buf][side][tid & 31][v] = hs[v];
+        } else {
+          T hf[Q][P], hU[P];
+          K::collide(src, row * nx + hx, sd.ph, ixi, Lam, ch, hf, hU);
+#pragma unroll
+          for (int v = 0; v < P; ++v) s_halo[buf][side][tid & 31][v] = side == 0 ? hf[0][v] : hf[1][v];
+        }
       }
     }
     // collide row r (r == y1 is the row above the band: only its -y population
     // is used); row y0 was loaded before the partials reduction
     if (PREFETCH) {
-      if (r < y1) {
-        const int yn = r + 1 < y1 ? r + 1 : map_index(y1, ny, sd.bcy);
-        K::load(src, yn * nx + xl, fnext);
-        if (K::COMP && r + 1 < y1) K::load_lo(src, yn * nx + xl, lonext);
+      if (r + 1 < y1) {
+        K::load(src, (r + 1) * nx + xl, fnext);
+        if (K::COMP) K::load_lo(src, (r + 1) * nx + xl, lonext);
+      } else if (r + 1 == y1) {
+        const long long ca = map_index(y1, ny, sd.bcy) * nx + xl;
+        if (PARTIAL) K::load_one(src, ca, 4, fnext[REST], fnext[4]);
+        else K::load(src, ca, fnext);
       }
     } else if (r > y0) {
-      const int yr = r < y1 ? r : map_index(y1, ny, sd.bcy);
-      K::load(src, yr * nx + xl, fraw);
-      if (K::COMP && r < y1) K::load_lo(src, yr * nx + xl, lo);
+      if (r < y1) {
+        K::load(src, r * nx + xl, fraw);
+        if (K::COMP) K::load_lo(src, r * nx + xl, lo);
+      } else {
+        const long long ca = map_index(y1, ny, sd.bcy) * nx + xl;
+        if (PARTIAL) K::load_one(src, ca, 4, fraw[REST], fraw[4]);
+        else K::load(src, ca, fraw);
+      }
     }
-    K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
+    if (PARTIAL && r == y1) K::template relax_one<1>(fraw[REST], fraw[4], false, sd.ph, ixi, Lam, ch, fs[4]);
+    else K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
     const int slot = r % 3;
     if (r < y1) {
 #pragma unroll
@@ -476,13 +533,14 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
       // finish row r-1
       const int rr = r - 1;
       const int ps = rr % 3;
-      const int hb = ((rr - y0) >> 5) & 1, hr = (rr - y0) & 31;
+      const int rb = (rr - y0) / hb;
+      const int hbuf = rb % 3, hr = rr - y0 - rb * hb;
       const long long cell = (long long)rr * nx + x;
       T Un[P];
 #pragma unroll
       for (int v = 0; v < P; ++v) {
-        const T a1 = tid > 0 ? s_ex[ps][0][v][tid - 1] : s_halo[hb][0][hr][v];
-        const T a2 = tid < W - 1 ? s_ex[ps][1][v][tid + 1] : s_halo[hb][1][hr][v];
+        const T a1 = tid > 0 ? s_ex[ps][0][v][tid - 1] : s_halo[hbuf][0][hr][v];
+        const T a2 = tid < W - 1 ? s_ex[ps][1][v][tid + 1] : s_halo[hbuf][1][hr][v];
         const T a4 = prev4[v];
         const T a5 = fs[4][v];
         dst[K::pidx(0 * P + v, cell)] = a1;

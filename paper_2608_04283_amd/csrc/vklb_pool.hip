@@ -196,7 +196,8 @@ vklb_status admit(vklb_pool* p) {
     r->slot = slot;
     p->slots[slot] = r;
     const int width = r->grid.dim == 1 ? 256 : 128;  // the batched kernels' tile widths
-    r->sd = make_desc(p->base + off, r->L, &r->sys, &r->grid, &r->speed, r->omega, r->bc, &r->eq, width, r->band);
+    r->sd = make_desc(p->base + off, r->L, &r->sys, &r->grid, &r->speed, r->omega, r->bc, &r->eq, width, r->band,
+                      default_halo(r->sys.kind));
     // initialization into the parity of the next round
     const long long cells = (long long)r->sd.nx * r->sd.ny;
     PCHK(p, hipMemcpyAsync(const_cast<double*>(r->sd.stage), r->U0.data(), r->U0.size() * 8, hipMemcpyHostToDevice,

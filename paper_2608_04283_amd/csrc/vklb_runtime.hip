@@ -315,7 +315,9 @@ vklb_status vklb_create(const vklb_system* sys, vklb_lattice lat, const vklb_gri
   if (band > 4096) band = 4096;
   s->chunk = s->opt.graph_chunk == 0 ? 64 : s->opt.graph_chunk;
   if (s->chunk > 0) s->chunk = (s->chunk + 1) / 2 * 2;  // even: replays start on parity 0
-  s->sd = make_desc(s->buf, L, sys, &s->grid, lambda, omega, s->bc, eq, width, band);
+  int halo = s->opt.halo_rows;
+  if (halo < 1 || halo > 32) halo = default_halo(sys->kind);
+  s->sd = make_desc(s->buf, L, sys, &s->grid, lambda, omega, s->bc, eq, width, band, halo);
   s->step_grid = s->sd.nblocks;
   *out = s;
   return VKLB_OK;

@@ -64,7 +64,7 @@ def run_batched(requests, budget_bytes, precision="fp32", chunk_rounds=32, realt
     results = {}
     cell_steps = 0
     n_done = 0
-    nonphysical = 0
+    failed = []
     t0 = time.perf_counter()
     try:
         while n_done < len(reqs):
@@ -85,7 +85,8 @@ def run_batched(requests, budget_bytes, precision="fp32", chunk_rounds=32, realt
                 latencies.append(t_done - arrival[c["tag"]])
                 cell_steps += c["problem"].cells * c["steps"]
                 n_done += 1
-                nonphysical += int(c["status"] != 0)
+                if c["status"] != 0:
+                    failed.append((c["tag"], c["problem"].name, c["fail_step"], c["fail_cell"]))
                 if keep_results:
                     results[c["tag"]] = (c["U"], c["t"], c["steps"], c["status"])
         makespan = time.perf_counter() - t0
@@ -96,7 +97,8 @@ def run_batched(requests, budget_bytes, precision="fp32", chunk_rounds=32, realt
     p50, p99 = _percentiles(latencies)
     return {"mode": "batched", "solves": n_done, "makespan_s": makespan, "solves_per_s": n_done / makespan,
             "p50_s": p50, "p99_s": p99, "cell_steps": cell_steps, "mcell_steps_per_s": cell_steps / makespan / 1e6,
-            "nonphysical": nonphysical, "arena_peak_bytes": stats["arena_peak"], "rounds": stats["rounds"],
+            "nonphysical": len(failed), "failed": failed, "arena_peak_bytes": stats["arena_peak"],
+            "rounds": stats["rounds"],
             "results": results if keep_results else None}
 
 
@@ -107,6 +109,7 @@ def run_plain(requests, precision="fp32", realtime=True, keep_results=False):
     latencies = []
     results = {}
     cell_steps = 0
+    failed = []
     t0 = time.perf_counter()
     try:
         for rq in reqs:
@@ -116,20 +119,29 @@ def run_plain(requests, precision="fp32", realtime=True, keep_results=False):
                 time.sleep(rq.arrival - now)
             s = vklb.Solver(prob, precision=precision, graph_chunk=-1)
             s.init()
-            U, t, n = s.run()
+            try:
+                U, t, n = s.run()
+                status = 0
+            except vklb.VklbError as e:
+                # a non-physical state ends the solve, as it does in the pool
+                if e.status != vklb.ERR_NONPHYSICAL:
+                    raise
+                d = s.diagnostics()
+                U, t, n, status = None, d["t"], d["steps"], e.status
+                failed.append((rq.rid, prob.name, d["fail_step"], d["fail_cell"]))
             s.close()
             t_done = time.perf_counter() - t0
             latencies.append(t_done - (rq.arrival if realtime else 0.0))
             cell_steps += prob.cells * n
             if keep_results:
-                results[rq.rid] = (U, t, n, 0)
+                results[rq.rid] = (U, t, n, status)
         makespan = time.perf_counter() - t0
     finally:
         pre.close()
     p50, p99 = _percentiles(latencies)
     return {"mode": "plain", "solves": len(reqs), "makespan_s": makespan, "solves_per_s": len(reqs) / makespan,
             "p50_s": p50, "p99_s": p99, "cell_steps": cell_steps, "mcell_steps_per_s": cell_steps / makespan / 1e6,
-            "results": results if keep_results else None}
+            "nonphysical": len(failed), "failed": failed, "results": results if keep_results else None}
 
 
 def with_arrivals(requests, rate, seed=7):

@@ -82,7 +82,7 @@ def test_invalid_basis_rejected(vk, prec, basis):
     """Basis is checked before any device call, so this runs without a GPU."""
     P = I.sod(100)
     sysd, lat, grid, speed, eq, bc = vk._structs(P)
-    opt = vk.Options(basis, 0, 0, 0)
+    opt = vk.Options(basis, 0, 0, 0, 0)
     h = ctypes.c_void_p()
     r = vk.lib().vklb_create(ctypes.byref(sysd), lat, ctypes.byref(grid), ctypes.byref(speed), P.omega, bc,
                              ctypes.byref(eq), vk.PRECISIONS[prec], ctypes.byref(opt), None, 0, None, ctypes.byref(h))

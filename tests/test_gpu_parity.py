@@ -100,11 +100,11 @@ def test_parity_with_oracle(gpu, oracle, name):
 @pytest.mark.parametrize("prec,basis", [("fp64", 0), ("fp32", 0), ("fp32", 3)])
 def test_tile_shapes_give_identical_results(gpu, prec, basis):
     """No cross-cell float reduction feeds back into the state, so every strip
-    width and band height gives the same bits."""
+    width, band height and halo batch gives the same bits."""
     P = rect_quadrants(300, 170, 5, 30)
     outs = []
-    for w, b in ((256, 32), (128, 8), (64, 64), (256, 17)):
-        s = gpu.Solver(P, precision=prec, basis=basis, strip_width=w, band_rows=b)
+    for w, b, h in ((256, 32, 0), (128, 8, 3), (64, 64, 1), (256, 17, 32), (256, 40, 2)):
+        s = gpu.Solver(P, precision=prec, basis=basis, strip_width=w, band_rows=b, halo_rows=h)
         s.init()
         outs.append(s.run()[0])
         s.close()
