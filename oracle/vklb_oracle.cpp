@@ -303,6 +303,36 @@ double alpha_weight(double lam, double lmax, double k) {
   return 1.0 / (1.0 + std::exp(-k * lam / lmax));
 }
 
+// MHD-GLM rows of the normal field B_d and of psi (Sec. 5.3). Their fluxes are
+// psi and c_h^2 B_d: functions of (B_d, psi) alone, so those two rows of the
+// Jacobian are zero outside the 2x2 block [[0, 1], [c_h^2, 0]], every
+// eigenvector of the other seven speeds has zero (B_d, psi) part, and the
+// (B_d, psi) rows of the weighted split come from the block alone. Written
+// out: speeds +-c_h, eigenvectors (1, +-c_h), expansion coefficients
+// phi_+- = (psi +- c_h B_d)/2. The generic eigen route above gives the same
+// rows up to rounding, but that rounding differs from cell to cell when
+// (B_d, psi) is uniform, and the +-c_h mode, which travels at the CFL speed
+// itself, then grows from it; taking the rows from the block keeps a uniform
+// (B_d, psi) exactly uniform, as it is in exact arithmetic.
+void glm_block_split(const or_config& cf, int d, const double* U, double ch, double lnorm, double* Fp, double* Fm) {
+  const int ib = 5 + d, ip = 8;
+  const double Bd = U[ib], psi = U[ip];
+  if (ch == 0.0) {
+    // no cleaning speed: both block speeds are 0 (weight 1/2 each)
+    Fp[ib] = 0.5 * psi;
+    Fm[ib] = 0.5 * psi;
+    Fp[ip] = 0.0;
+    Fm[ip] = 0.0;
+    return;
+  }
+  const double php = 0.5 * (psi + ch * Bd), phm = 0.5 * (psi - ch * Bd);
+  const double ap = alpha_weight(ch, lnorm, cf.k), am = alpha_weight(-ch, lnorm, cf.k);
+  Fp[ib] = ap * php + am * phm;
+  Fp[ip] = ap * php * ch - am * phm * ch;
+  Fm[ib] = (1.0 - ap) * php + (1.0 - am) * phm;
+  Fm[ip] = (1.0 - ap) * php * ch - (1.0 - am) * phm * ch;
+}
+
 // Weighted flux-vector split of F^(d)(U) (Sec. 2.2 expansion, Sec. 3.1 weights).
 // Lam is the global max |lambda| over cells, directions and eigenvalues of the
 // current state; it normalizes the sigmoid unless alpha_norm selects the
@@ -350,6 +380,7 @@ bool split(const or_config& cf, int d, const double* U, double ch, double Lam, d
     Fp[i] = sp;
     Fm[i] = sm;
   }
+  if (cf.kind == SYS_MHD) glm_block_split(cf, d, U, ch, lnorm, Fp, Fm);
   for (int i = 0; i < p; ++i)
     if (!std::isfinite(Fp[i]) || !std::isfinite(Fm[i])) return false;
   return true;

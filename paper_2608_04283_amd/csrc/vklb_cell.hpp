@@ -55,10 +55,53 @@ template <class S>
 __host__ __device__ inline S sq(S a) { return a * a; }
 
 // beta(lambda) = alpha(lambda) - 1/2 for the sigmoid of Sec. 3.1.
+// Division, reciprocal and square root of the per-cell arithmetic. FP32
+// device code uses the hardware reciprocal and square root (about 1 ulp),
+// as plain operations the compiler cannot fuse differently in different
+// places, so every inlined copy still rounds identically; FP64, and host
+// code, use the correctly rounded operations.
+template <class S>
+__host__ __device__ inline S qrcp(S b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (sizeof(S) == 4) return __builtin_amdgcn_rcpf(b);
+#endif
+  return S(1) / b;
+}
+template <class S>
+__host__ __device__ inline S qdiv(S a, S b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (sizeof(S) == 4) return a * __builtin_amdgcn_rcpf(b);
+#endif
+  return a / b;
+}
+template <class S>
+__host__ __device__ inline S qsqrt(S x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (sizeof(S) == 4) return __builtin_amdgcn_sqrtf(x);
+#endif
+  return sqrt(x);
+}
+
+// tanh for the weights. FP32 device code evaluates it from its exponential
+// form, tanh z = sign(z) (1 - e^{-2|z|}) / (1 + e^{-2|z|}), with the hardware
+// base-2 exponential and reciprocal: a few units in the last place (absolute
+// error ~1e-7 near z = 0), far inside the FP32 path's tolerance, and an odd
+// function exactly as tanh is. FP64, and host code, call the library tanh.
+template <class S>
+__host__ __device__ inline S wtanh(S z) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (sizeof(S) == 4) {
+    const float t = __builtin_amdgcn_exp2f(-2.8853900817779268f * fabsf(z));  // e^{-2|z|}
+    return copysignf((1.0f - t) * __builtin_amdgcn_rcpf(1.0f + t), z);
+  }
+#endif
+  return tanh(z);
+}
+
 template <class S>
 __host__ __device__ inline S beta_w(S lam, S half_k_over_L, int kinf) {
   if (kinf) return lam >= S(0) ? S(0.5) : S(-0.5);
-  return S(0.5) * tanh(lam * half_k_over_L);
+  return S(0.5) * wtanh(lam * half_k_over_L);
 }
 
 // Divided difference (beta(a) - beta(b)) / (a - b) from the weights ba, bb
@@ -67,8 +110,8 @@ template <class S>
 __host__ __device__ inline S beta_dd(S a, S ba, S b, S bb, S half_k_over_L, int kinf) {
   const S d = a - b;
   const S rel = sizeof(S) == 4 ? S(1e-3) : S(1e-6);
-  if (fabs(d) > rel * (fabs(a) + fabs(b)) || kinf) return d != S(0) ? (ba - bb) / d : S(0);
-  const S tm = tanh(S(0.5) * (a + b) * half_k_over_L);
+  if (fabs(d) > rel * (fabs(a) + fabs(b)) || kinf) return d != S(0) ? qdiv(ba - bb, d) : S(0);
+  const S tm = wtanh(S(0.5) * (a + b) * half_k_over_L);
   return S(0.5) * half_k_over_L * (S(1) - tm * tm);
 }
 
@@ -93,7 +136,7 @@ struct Cell<K_LINEAR, DIM, S> {
   __host__ __device__ static void split(int d, const S* U, const Phys& ph, S Lam, S, S* F, S* D) {
     S a = S(ph.adv[d]);
     S L = ph.alpha_local ? fabs(a) : Lam;
-    S hk = L > S(0) ? S(0.5 * ph.k) / L : S(0);
+    S hk = L > S(0) ? qdiv(S(0.5 * ph.k), L) : S(0);
     F[0] = a * U[0];
     D[0] = beta_w(a, hk, ph.kinf) * a * U[0];
   }
@@ -105,9 +148,9 @@ struct Cell<K_SW, DIM, S> {
   static constexpr int P = DIM + 1;
   __host__ __device__ static void speeds(const S* U, const Phys& ph, S* lam, S* cfm) {
     S h = U[0];
-    S c = sqrt(S(ph.g) * h);
+    S c = qsqrt(S(ph.g) * h);
     S m = S(0);
-    for (int d = 0; d < DIM; ++d) m = fmax(m, fabs(U[1 + d] / h) + c);
+    for (int d = 0; d < DIM; ++d) m = fmax(m, fabs(qdiv(U[1 + d], h)) + c);
     *lam = m;
     *cfm = S(0);
   }
@@ -119,19 +162,19 @@ struct Cell<K_SW, DIM, S> {
   __host__ __device__ static void split(int d, const S* U, const Phys& ph, S Lam, S, S* F, S* D) {
     const S h = U[0];
     const S g = S(ph.g);
-    const S ud = U[1 + d] / h;
-    const S c = sqrt(g * h);
+    const S ud = qdiv(U[1 + d], h);
+    const S c = qsqrt(g * h);
     F[0] = U[1 + d];
     for (int kk = 0; kk < DIM; ++kk) F[1 + kk] = U[1 + kk] * ud;
     F[1 + d] += S(0.5) * g * h * h;
     const S lm = ud - c, lp = ud + c;
     const S L = ph.alpha_local ? fmax(fabs(lm), fabs(lp)) : Lam;
-    const S hk = L > S(0) ? S(0.5 * ph.k) / L : S(0);
+    const S hk = L > S(0) ? qdiv(S(0.5 * ph.k), L) : S(0);
     // coefficients of the two acoustic waves: phi = h (2 u_d -+ c) / 4
     const S wm = beta_w(lm, hk, ph.kinf) * h * (S(2) * ud - c) * S(0.25);
     const S wp = beta_w(lp, hk, ph.kinf) * h * (S(2) * ud + c) * S(0.25);
     D[0] = wm + wp;
-    for (int kk = 0; kk < DIM; ++kk) D[1 + kk] = (U[1 + kk] / h) * (wm + wp);
+    for (int kk = 0; kk < DIM; ++kk) D[1 + kk] = qdiv(U[1 + kk], h) * (wm + wp);
     D[1 + d] = lm * wm + lp * wp;
   }
 };
@@ -143,14 +186,14 @@ struct Cell<K_EULER, DIM, S> {
   __host__ __device__ static S pressure(const S* U, S gamma) {
     S m2 = S(0);
     for (int kk = 0; kk < DIM; ++kk) m2 += U[1 + kk] * U[1 + kk];
-    return (gamma - S(1)) * (U[DIM + 1] - S(0.5) * m2 / U[0]);
+    return (gamma - S(1)) * (U[DIM + 1] - S(0.5) * qdiv(m2, U[0]));
   }
   __host__ __device__ static void speeds(const S* U, const Phys& ph, S* lam, S* cfm) {
     const S gamma = S(ph.gamma);
     const S rho = U[0];
-    const S c = sqrt(gamma * pressure(U, gamma) / rho);
+    const S c = qsqrt(qdiv(gamma * pressure(U, gamma), rho));
     S m = S(0);
-    for (int d = 0; d < DIM; ++d) m = fmax(m, fabs(U[1 + d] / rho) + c);
+    for (int d = 0; d < DIM; ++d) m = fmax(m, fabs(qdiv(U[1 + d], rho)) + c);
     *lam = m;
     *cfm = S(0);
   }
@@ -162,13 +205,13 @@ struct Cell<K_EULER, DIM, S> {
   __host__ __device__ static void split(int d, const S* U, const Phys& ph, S Lam, S, S* F, S* D) {
     const S gamma = S(ph.gamma);
     const S rho = U[0];
-    const S irho = S(1) / rho;
+    const S irho = qrcp(rho);
     S vel[DIM];
     S v2 = S(0);
     for (int kk = 0; kk < DIM; ++kk) { vel[kk] = U[1 + kk] * irho; v2 += vel[kk] * vel[kk]; }
     const S E = U[DIM + 1];
     const S p = (gamma - S(1)) * (E - S(0.5) * rho * v2);
-    const S c = sqrt(gamma * p * irho);
+    const S c = qsqrt(gamma * p * irho);
     const S ud = vel[d];
     F[0] = U[1 + d];
     for (int kk = 0; kk < DIM; ++kk) F[1 + kk] = U[1 + kk] * ud;
@@ -176,12 +219,12 @@ struct Cell<K_EULER, DIM, S> {
     F[DIM + 1] = (E + p) * ud;
     const S l1 = ud - c, l3 = ud + c;
     const S L = ph.alpha_local ? fmax(fabs(l1), fabs(l3)) : Lam;
-    const S hk = L > S(0) ? S(0.5 * ph.k) / L : S(0);
+    const S hk = L > S(0) ? qdiv(S(0.5 * ph.k), L) : S(0);
     const S mu1 = beta_w(l1, hk, ph.kinf) * l1;
     const S mu2 = beta_w(ud, hk, ph.kinf) * ud;
     const S mu3 = beta_w(l3, hk, ph.kinf) * l3;
     const S H = (E + p) * irho;
-    const S s = rho / (S(2) * gamma);
+    const S s = qdiv(rho, S(2) * gamma);
     const S ent = S(2) * (gamma - S(1)) * mu2;
     D[0] = s * (ent + mu1 + mu3);
     for (int kk = 0; kk < DIM; ++kk) D[1 + kk] = s * (ent + mu1 + mu3) * vel[kk];
@@ -199,23 +242,23 @@ struct Cell<K_MHD, DIM, S> {
   __host__ __device__ static S pressure(const S* U, S gamma) {
     S m2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
     S B2 = U[5] * U[5] + U[6] * U[6] + U[7] * U[7];
-    return (gamma - S(1)) * (U[4] - S(0.5) * m2 / U[0] - S(0.5) * B2);
+    return (gamma - S(1)) * (U[4] - S(0.5) * qdiv(m2, U[0]) - S(0.5) * B2);
   }
   // fast speed along direction d
   __host__ __device__ static S fast(const S* U, S gamma, int d) {
     const S rho = U[0];
-    const S a2 = gamma * pressure(U, gamma) / rho;
-    const S bn2 = U[5 + d] * U[5 + d] / rho;
-    const S bt2 = (U[5] * U[5] + U[6] * U[6] + U[7] * U[7]) / rho - bn2;
-    const S disc = sqrt(sq(a2 - bn2) + bt2 * (S(2) * a2 + S(2) * bn2 + bt2));
-    return sqrt(S(0.5) * (a2 + bn2 + bt2 + disc));
+    const S a2 = qdiv(gamma * pressure(U, gamma), rho);
+    const S bn2 = qdiv(U[5 + d] * U[5 + d], rho);
+    const S bt2 = qdiv(U[5] * U[5] + U[6] * U[6] + U[7] * U[7], rho) - bn2;
+    const S disc = qsqrt(sq(a2 - bn2) + bt2 * (S(2) * a2 + S(2) * bn2 + bt2));
+    return qsqrt(S(0.5) * (a2 + bn2 + bt2 + disc));
   }
   __host__ __device__ static void speeds(const S* U, const Phys& ph, S* lam, S* cfm) {
     const S gamma = S(ph.gamma);
     S m = S(0), cm = S(0);
     for (int d = 0; d < DIM; ++d) {
       const S cf = fast(U, gamma, d);
-      m = fmax(m, fabs(U[1 + d] / U[0]) + cf);
+      m = fmax(m, fabs(qdiv(U[1 + d], U[0])) + cf);
       cm = fmax(cm, cf);
     }
     *lam = m;   // seven-wave max; the cleaning speed joins it globally
@@ -239,15 +282,15 @@ struct Cell<K_MHD, DIM, S> {
     const S xvq = -w.bz * x[2] + w.by * x[3];
     const S xbp = w.by * x[5] + w.bz * x[6];
     const S xbq = -w.bz * x[5] + w.by * x[6];
-    const S X = x[4] / (w.rho * w.a2);
-    const S Y = xbp / (w.a * w.sr);
+    const S X = qdiv(x[4], w.rho * w.a2);
+    const S Y = qdiv(xbp, w.a * w.sr);
     const S Fp = w.af * X + w.as * Y;
     const S Sp = w.as * X - w.af * Y;
     const S Z1 = x[1], Z2 = w.sgn * xvp;
-    const S ia2 = S(1) / w.a2;
+    const S ia2 = qrcp(w.a2);
     const S Fm = (w.af * w.cf * Z1 - w.as * w.cs * Z2) * ia2;
     const S Sm = (w.as * w.cs * Z1 + w.af * w.cf * Z2) * ia2;
-    const S Ap = xbq / w.sr, Am = -w.sgn * xvq;
+    const S Ap = qdiv(xbq, w.sr), Am = -w.sgn * xvq;
     c[0] = S(0.5) * (Fp - Fm);
     c[6] = S(0.5) * (Fp + Fm);
     c[2] = S(0.5) * (Sp - Sm);
@@ -280,9 +323,9 @@ struct Cell<K_MHD, DIM, S> {
   // vanishes. The FP32 split computes their eigenstructure in FP64.
   __host__ __device__ static bool near_degenerate(int d, const S* U, S gamma) {
     const S rho = U[0];
-    const S a2 = gamma * pressure(U, gamma) / rho;
-    const S bn2 = U[5 + d] * U[5 + d] / rho;
-    const S bt2 = (U[5] * U[5] + U[6] * U[6] + U[7] * U[7]) / rho - bn2;
+    const S a2 = qdiv(gamma * pressure(U, gamma), rho);
+    const S bn2 = qdiv(U[5 + d] * U[5 + d], rho);
+    const S bt2 = qdiv(U[5] * U[5] + U[6] * U[6] + U[7] * U[7], rho) - bn2;
     const S tot = a2 + bn2 + bt2;
     const S disc2 = sq(a2 - bn2) + bt2 * (S(2) * a2 + S(2) * bn2 + bt2);
     return disc2 < S(1e-4) * tot * tot || bt2 < S(1e-4) * tot || bn2 < S(1e-4) * tot;
@@ -291,28 +334,28 @@ struct Cell<K_MHD, DIM, S> {
   // Wave speeds and Roe-Balsara normalization of one direction, in precision R.
   template <class R>
   __host__ __device__ static void eigenstructure(R rho, R p, R Bn, R By, R Bz, R gamma, R* out) {
-    const R irho = R(1) / rho;
+    const R irho = qrcp(rho);
     const R a2 = gamma * p * irho;
     const R bn2 = Bn * Bn * irho;
     const R bt2r = By * By + Bz * Bz;
     const R bt2 = bt2r * irho;
     const R b2 = bn2 + bt2;
-    const R disc = sqrt(sq(a2 - bn2) + bt2 * (R(2) * a2 + R(2) * bn2 + bt2));
+    const R disc = qsqrt(sq(a2 - bn2) + bt2 * (R(2) * a2 + R(2) * bn2 + bt2));
     const R cf2 = R(0.5) * (a2 + b2 + disc);
-    const R cs2 = cf2 > R(0) ? a2 * bn2 / cf2 : R(0);
+    const R cs2 = cf2 > R(0) ? qdiv(a2 * bn2, cf2) : R(0);
     R af, as, by, bz;
     if (disc > R(0)) {
       const R diff = a2 - b2;
-      const R nf = diff >= R(0) ? R(0.5) * (diff + disc) : R(2) * a2 * bt2 / (disc - diff);
-      const R ns = diff <= R(0) ? R(0.5) * (disc - diff) : R(2) * a2 * bt2 / (disc + diff);
-      af = sqrt(fmin(R(1), fmax(R(0), nf / disc)));
-      as = sqrt(fmin(R(1), fmax(R(0), ns / disc)));
+      const R nf = diff >= R(0) ? R(0.5) * (diff + disc) : qdiv(R(2) * a2 * bt2, disc - diff);
+      const R ns = diff <= R(0) ? R(0.5) * (disc - diff) : qdiv(R(2) * a2 * bt2, disc + diff);
+      af = qsqrt(fmin(R(1), fmax(R(0), qdiv(nf, disc))));
+      as = qsqrt(fmin(R(1), fmax(R(0), qdiv(ns, disc))));
     } else {
       af = R(1);
       as = R(0);
     }
     if (bt2r > R(0)) {
-      const R ibt = R(1) / sqrt(bt2r);
+      const R ibt = qrcp(qsqrt(bt2r));
       by = By * ibt;
       bz = Bz * ibt;
     } else {
@@ -320,10 +363,10 @@ struct Cell<K_MHD, DIM, S> {
       bz = R(0.70710678118654752440);
     }
     out[0] = a2;
-    out[1] = sqrt(a2);
-    out[2] = sqrt(cf2);
-    out[3] = sqrt(cs2);
-    out[4] = sqrt(bn2);
+    out[1] = qsqrt(a2);
+    out[2] = qsqrt(cf2);
+    out[3] = qsqrt(cs2);
+    out[4] = qsqrt(bn2);
     out[5] = af;
     out[6] = as;
     out[7] = by;
@@ -336,7 +379,7 @@ struct Cell<K_MHD, DIM, S> {
     // local frame: n = d, t1 = the other in-plane axis, t2 = z
     const int n = d, t1 = 1 - d, t2 = 2;
     const S rho = Ug[0];
-    const S irho = S(1) / rho;
+    const S irho = qrcp(rho);
     const S u = Ug[1 + n] * irho, v = Ug[1 + t1] * irho, w = Ug[1 + t2] * irho;
     const S E = Ug[4];
     const S Bn = Ug[5 + n], By = Ug[5 + t1], Bz = Ug[5 + t2];
@@ -361,7 +404,7 @@ struct Cell<K_MHD, DIM, S> {
     // speeds nearly coincide get this eigenstructure in FP64
     Waves W;
     W.rho = rho;
-    W.sr = sqrt(rho);
+    W.sr = qsqrt(rho);
     S eg[9];
     if (sizeof(S) == 4 && near_degenerate(d, Ug, gamma)) {
       double e64[9];
@@ -383,7 +426,7 @@ struct Cell<K_MHD, DIM, S> {
     // speeds (f-, a-, s-, e, s+, a+, f+)
     S lam[7] = {u - W.cf, u - ca, u - W.cs, u, u + W.cs, u + ca, u + W.cf};
     const S L = ph.alpha_local ? fmax(fmax(fabs(lam[0]), fabs(lam[6])), ch) : Lam;
-    const S hk = L > S(0) ? S(0.5 * ph.k) / L : S(0);
+    const S hk = L > S(0) ? qdiv(S(0.5 * ph.k), L) : S(0);
     // primitive images of the seven-wave flux and of the B_n column of the Jacobian
     S xF[7], xC[7];
     xF[0] = F[0];
@@ -418,7 +461,7 @@ struct Cell<K_MHD, DIM, S> {
     D[1] = u * y[0] + rho * y[1];
     D[2] = v * y[0] + rho * y[2];
     D[3] = w * y[0] + rho * y[3];
-    D[4] = y[4] / gm1 + S(0.5) * uu * y[0] + rho * (u * y[1] + v * y[2] + w * y[3]) + By * y[5] + Bz * y[6];
+    D[4] = qdiv(y[4], gm1) + S(0.5) * uu * y[0] + rho * (u * y[1] + v * y[2] + w * y[3]) + By * y[5] + Bz * y[6];
     D[6] = y[5];
     D[7] = y[6];
     const S eta = bcp * ch;

@@ -97,7 +97,7 @@ inline int default_width(int dim, long long nx) {
 // compute unit, so it takes short bands to have enough of them.
 inline int default_band(int kind) { return kind == VKLB_MHD_GLM ? 8 : 32; }
 // Rows of halo columns per batch (1..32).
-inline int default_halo(int kind) { return kind == VKLB_MHD_GLM ? 8 : 4; }
+inline int default_halo(int kind) { return kind == VKLB_MHD_GLM ? 8 : 2; }
 
 inline int step_grid_of(const vklb_grid* g, int width, int band) {
   if (g->dim == 1) return int((g->n[0] + width - 3) / (width - 2));

@@ -300,15 +300,18 @@ def test_smooth_wave_second_order_at_omega_two(oracle):
 
 def test_brio_wu_invariants(oracle):
     """MHD shock tube (Sec. 5.3): the cleaning pair (B_x, psi) is decoupled and
-    uniform, so B_x stays 0.75 and psi stays 0 to rounding; w and B_z stay
-    exactly 0; the state stays admissible."""
+    uniform, so B_x stays 0.75 and psi stays 0 to rounding and both stay
+    exactly uniform (their split rows depend on (B_x, psi) alone, the same
+    arithmetic in every cell); w and B_z stay exactly 0; the state stays
+    admissible. Uniformity matters: the +-c_h mode travels at the CFL speed
+    and grows from any cell-to-cell rounding."""
     O = oracle
     P = I.brio_wu(256)
     r = O.run(cfg_of(O, P), P.U0)
     assert r["status"] == 0 and r["t"] == 0.1
     U = r["U"]
-    assert np.max(np.abs(U[5] - 0.75)) < 1e-12
-    assert np.max(np.abs(U[8])) < 1e-12
+    assert np.all(U[5] == U[5][0]) and abs(U[5][0] - 0.75) < 1e-14
+    assert np.all(U[8] == U[8][0]) and abs(U[8][0]) < 1e-13
     assert np.all(U[3] == 0.0) and np.all(U[7] == 0.0)
     assert np.all(U[0] > 0)
 
