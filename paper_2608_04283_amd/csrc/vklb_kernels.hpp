@@ -433,18 +433,20 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   const int xl = map_index(x < nx + 1 ? x : nx, nx, sd.bcx);
   const long long n0 = sd.st->S[sd.par].n;
   const T* __restrict__ src = (const T*)((n0 & 1) ? sd.fb : sd.fa);
-  // stored values of row y0 - 1 (only its +y population is used) and of row y0
   // Systems with few values per cell (SW, Euler) load row r + 1 while row r
   // is collided, so a row's memory latency overlaps the previous row's work;
   // MHD has no registers to spare for it.
   constexpr bool PREFETCH = Q * P <= 20;
-  // In the delta bases the rows y0 - 1 and y1 and the halo columns, of which
-  // one population each is used, load only U and that population (SW and
-  // Euler; for MHD the extra code paths cost more registers than it saves).
-  constexpr bool PARTIAL = DELTA && PREFETCH;
+  // In the delta bases the rows y0 - 1 and y1 and the halo columns use one
+  // population each: they load only U and that population and collide it with
+  // the split of its axis alone.
+  constexpr bool PARTIAL = DELTA;
+  const long long below = (long long)map_index(y0 - 1, ny, sd.bcy) * nx + xl;
+  const long long above = (long long)map_index(y1, ny, sd.bcy) * nx + xl;
+  // stored values of row y0 - 1 (only its +y population is used) and of row y0
   T fbelow[Q][P], fraw[Q][P], lo[P], fnext[Q][P], lonext[P];
-  if (PARTIAL) K::load_one(src, map_index(y0 - 1, ny, sd.bcy) * nx + xl, 3, fbelow[REST], fbelow[3]);
-  else K::load(src, map_index(y0 - 1, ny, sd.bcy) * nx + xl, fbelow);
+  if (PARTIAL) K::load_one(src, below, 3, fbelow[REST], fbelow[3]);
+  else K::load(src, below, fbelow);
   K::load(src, y0 * nx + xl, fraw);
   K::load_lo(src, y0 * nx + xl, lo);
   const Step S = begin_step(sd, red);
@@ -478,9 +480,43 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   // the same cells, so those come from L2. Three batch buffers keep a batch
   // from being overwritten while a slower wave still reads it.
   const int hb = sd.halo;
-  for (int r = y0; r <= y1; ++r) {
+
+  // Finish row rr = r - 1: gather the populations streaming into it (+x/-x
+  // from LDS, +y kept from row r - 2, -y of row r in fs[4]), store them and
+  // U^{n+1}, and take the new state's speeds.
+  auto finish = [&](int r) {
+    const int rr = r - 1;
+    const int ps = rr % 3;
+    const int rb = (rr - y0) / hb;
+    const int hbuf = rb % 3, hr = rr - y0 - rb * hb;
+    const long long cell = (long long)rr * nx + x;
+    T Un[P];
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+      const T a1 = tid > 0 ? s_ex[ps][0][v][tid - 1] : s_halo[hbuf][0][hr][v];
+      const T a2 = tid < W - 1 ? s_ex[ps][1][v][tid + 1] : s_halo[hbuf][1][hr][v];
+      const T a4 = prev4[v];
+      const T a5 = fs[4][v];
+      dst[K::pidx(0 * P + v, cell)] = a1;
+      dst[K::pidx(1 * P + v, cell)] = a2;
+      dst[K::pidx(3 * P + v, cell)] = a4;
+      dst[K::pidx(4 * P + v, cell)] = a5;
+      if (DELTA) {
+        const T b1 = s_ex[ps][0][v][tid], b2 = s_ex[ps][1][v][tid];
+        T lo_new;
+        Un[v] = K::advance(c_rest[v], ((a1 - b1) + (a2 - b2)) + ((a4 - c4[v]) + (a5 - c5[v])), c_lo[v], lo_new);
+        if (K::COMP) dst[K::pidx(Q * P + v, cell)] = lo_new;
+      } else {
+        Un[v] = ((((T(0) + a1) + a2) + c_rest[v]) + a4) + a5;
+      }
+      dst[K::pidx(REST * P + v, cell)] = DELTA ? Un[v] : c_rest[v];
+    }
+    K::new_state(sd, Un, cell, n + 1, lam, cfm);
+  };
+
+  for (int r = y0; r < y1; ++r) {
     const int bq = (r - y0) / hb;
-    if (r < y1 && r - y0 == bq * hb && tid < 64) {
+    if (r - y0 == bq * hb && tid < 64) {
       const int buf = bq % 3;
       const int side = tid >> 5;
       const int row = r + (tid & 31);
@@ -500,65 +536,26 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
         }
       }
     }
-    // collide row r (r == y1 is the row above the band: only its -y population
-    // is used); row y0 was loaded before the partials reduction
+    // collide row r; row y0 was loaded before the partials reduction
     if (PREFETCH) {
       if (r + 1 < y1) {
         K::load(src, (r + 1) * nx + xl, fnext);
         if (K::COMP) K::load_lo(src, (r + 1) * nx + xl, lonext);
-      } else if (r + 1 == y1) {
-        const long long ca = map_index(y1, ny, sd.bcy) * nx + xl;
-        if (PARTIAL) K::load_one(src, ca, 4, fnext[REST], fnext[4]);
-        else K::load(src, ca, fnext);
+      } else if (PARTIAL) {
+        K::load_one(src, above, 4, fnext[REST], fnext[4]);
+      } else {
+        K::load(src, above, fnext);
       }
     } else if (r > y0) {
-      if (r < y1) {
-        K::load(src, r * nx + xl, fraw);
-        if (K::COMP) K::load_lo(src, r * nx + xl, lo);
-      } else {
-        const long long ca = map_index(y1, ny, sd.bcy) * nx + xl;
-        if (PARTIAL) K::load_one(src, ca, 4, fraw[REST], fraw[4]);
-        else K::load(src, ca, fraw);
-      }
+      K::load(src, r * nx + xl, fraw);
+      if (K::COMP) K::load_lo(src, r * nx + xl, lo);
     }
-    if (PARTIAL && r == y1) K::template relax_one<1>(fraw[REST], fraw[4], false, sd.ph, ixi, Lam, ch, fs[4]);
-    else K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
+    K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
     const int slot = r % 3;
-    if (r < y1) {
 #pragma unroll
-      for (int v = 0; v < P; ++v) { s_ex[slot][0][v][tid] = fs[0][v]; s_ex[slot][1][v][tid] = fs[1][v]; }
-    }
+    for (int v = 0; v < P; ++v) { s_ex[slot][0][v][tid] = fs[0][v]; s_ex[slot][1][v][tid] = fs[1][v]; }
     __syncthreads();
-    if (r > y0 && x < nx) {
-      // finish row r-1
-      const int rr = r - 1;
-      const int ps = rr % 3;
-      const int rb = (rr - y0) / hb;
-      const int hbuf = rb % 3, hr = rr - y0 - rb * hb;
-      const long long cell = (long long)rr * nx + x;
-      T Un[P];
-#pragma unroll
-      for (int v = 0; v < P; ++v) {
-        const T a1 = tid > 0 ? s_ex[ps][0][v][tid - 1] : s_halo[hbuf][0][hr][v];
-        const T a2 = tid < W - 1 ? s_ex[ps][1][v][tid + 1] : s_halo[hbuf][1][hr][v];
-        const T a4 = prev4[v];
-        const T a5 = fs[4][v];
-        dst[K::pidx(0 * P + v, cell)] = a1;
-        dst[K::pidx(1 * P + v, cell)] = a2;
-        dst[K::pidx(3 * P + v, cell)] = a4;
-        dst[K::pidx(4 * P + v, cell)] = a5;
-        if (DELTA) {
-          const T b1 = s_ex[ps][0][v][tid], b2 = s_ex[ps][1][v][tid];
-          T lo_new;
-          Un[v] = K::advance(c_rest[v], ((a1 - b1) + (a2 - b2)) + ((a4 - c4[v]) + (a5 - c5[v])), c_lo[v], lo_new);
-          if (K::COMP) dst[K::pidx(Q * P + v, cell)] = lo_new;
-        } else {
-          Un[v] = ((((T(0) + a1) + a2) + c_rest[v]) + a4) + a5;
-        }
-        dst[K::pidx(REST * P + v, cell)] = DELTA ? Un[v] : c_rest[v];
-      }
-      K::new_state(sd, Un, cell, n + 1, lam, cfm);
-    }
+    if (r > y0 && x < nx) finish(r);
     if (r > y0) {
 #pragma unroll
       for (int v = 0; v < P; ++v) prev4[v] = c4[v];
@@ -570,7 +567,7 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
       c4[v] = fs[3][v];
       c5[v] = fs[4][v];
     }
-    if (PREFETCH && r < y1) {
+    if (PREFETCH) {
 #pragma unroll
       for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -581,6 +578,15 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
       }
     }
   }
+  // The row above the band: only its -y population is used; it finishes row
+  // y1 - 1 (whose LDS values were published before the last barrier).
+  if (!PREFETCH) {
+    if (PARTIAL) K::load_one(src, above, 4, fraw[REST], fraw[4]);
+    else K::load(src, above, fraw);
+  }
+  if (PARTIAL) K::template relax_one<1>(fraw[REST], fraw[4], false, sd.ph, ixi, Lam, ch, fs[4]);
+  else K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
+  if (x < nx) finish(y1);
   block_max2(lam, cfm, red);
   end_step(sd, S, tile, lam, cfm);
 }
