@@ -8,7 +8,11 @@
 // Execution: a round is one batched launch per system class over the work
 // list of (solve slot, tile) items of every resident solve of that class.
 // All resident solves share the round parity; a solve admitted before round
-// r is initialized into parity r & 1.
+// r is initialized into parity r & 1. A class's round depends only on that
+// class's previous round, so each class runs on a stream of its own and small
+// 1D rounds overlap the large 2D ones; the caller's stream (admission,
+// initialization, status, harvest) and the class streams are joined by events
+// at both ends of vklb_pool_run.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -146,6 +150,9 @@ struct vklb_pool {
   vklb_precision prec = VKLB_FP32;
   int basis[3] = {0, 0, 0};  // stored basis per dimension (index 1, 2)
   hipStream_t stream = nullptr;
+  hipStream_t cls_stream[kClasses] = {};   // default priority, non-blocking
+  hipEvent_t ev_main = nullptr;
+  hipEvent_t ev_cls[kClasses] = {};
   int device = 0;
   uint64_t next_ticket = 1;
   std::deque<Req*> queue;
@@ -293,6 +300,11 @@ vklb_status vklb_pool_create(size_t hbm_budget, vklb_precision prec, void* hip_s
   if ((e = hipMalloc(&p->d_status, sizeof(SlotStatus) * kMaxSlots)) != hipSuccess) return cleanup(e);
   if ((e = hipHostMalloc(&p->h_status, sizeof(SlotStatus) * kMaxSlots, hipHostMallocDefault)) != hipSuccess)
     return cleanup(e);
+  for (int c = 0; c < kClasses; ++c) {
+    if ((e = hipStreamCreateWithFlags(&p->cls_stream[c], hipStreamNonBlocking)) != hipSuccess) return cleanup(e);
+    if ((e = hipEventCreateWithFlags(&p->ev_cls[c], hipEventDisableTiming)) != hipSuccess) return cleanup(e);
+  }
+  if ((e = hipEventCreateWithFlags(&p->ev_main, hipEventDisableTiming)) != hipSuccess) return cleanup(e);
   p->arena.reset(p->budget);
   for (int kind = 0; kind < 4; ++kind)
     for (int dim = 1; dim <= 2; ++dim)
@@ -346,14 +358,21 @@ vklb_status vklb_pool_run(vklb_pool* p, int rounds) {
   if (st != VKLB_OK) return st;
   st = upload_lists(p);
   if (st != VKLB_OK) return st;
-  for (int k = 0; k < rounds; ++k) {
-    const int par = int(p->round & 1);
-    for (int c = 0; c < kClasses; ++c) {
-      if (!p->nwork[c]) continue;
-      PCHK(p, p->cls_launch[c].batched(p->d_descs, p->d_work[c], p->d_nwork + c, par, p->nwork[c], p->stream));
+  if (rounds == 0) return VKLB_OK;
+  // class streams start after the caller's stream (admission, lists) ...
+  PCHK(p, hipEventRecord(p->ev_main, p->stream));
+  for (int c = 0; c < kClasses; ++c) {
+    if (!p->nwork[c]) continue;
+    PCHK(p, hipStreamWaitEvent(p->cls_stream[c], p->ev_main, 0));
+    for (int k = 0; k < rounds; ++k) {
+      const int par = int((p->round + k) & 1);
+      PCHK(p, p->cls_launch[c].batched(p->d_descs, p->d_work[c], p->d_nwork + c, par, p->nwork[c], p->cls_stream[c]));
     }
-    p->round++;
+    // ... and the caller's stream continues after every class's rounds
+    PCHK(p, hipEventRecord(p->ev_cls[c], p->cls_stream[c]));
+    PCHK(p, hipStreamWaitEvent(p->stream, p->ev_cls[c], 0));
   }
+  p->round += rounds;
   p->stats.rounds = p->round;
   return VKLB_OK;
 }
@@ -436,6 +455,14 @@ void vklb_pool_destroy(vklb_pool* p) {
   else (void)hipDeviceSynchronize();
   for (Req* r : p->queue) delete r;
   for (Req* r : p->slots) delete r;
+  for (int c = 0; c < kClasses; ++c) {
+    if (p->cls_stream[c]) {
+      (void)hipStreamSynchronize(p->cls_stream[c]);
+      (void)hipStreamDestroy(p->cls_stream[c]);
+    }
+    if (p->ev_cls[c]) (void)hipEventDestroy(p->ev_cls[c]);
+  }
+  if (p->ev_main) (void)hipEventDestroy(p->ev_main);
   for (int c = 0; c < kClasses; ++c)
     if (p->d_work[c]) (void)hipFree(p->d_work[c]);
   if (p->d_descs) (void)hipFree(p->d_descs);
