@@ -193,6 +193,25 @@ vklb_status vklb_last_step_ms(vklb_solver* s, double* ms);
 
 void vklb_destroy(vklb_solver* s);
 
+/* Autotuner of the tile shape. Times `steps` steps (after a short warm-up) of
+ * the given solve from U0_host (FP64 SoA [p][cells], host) for each candidate
+ * shape and writes the fastest options to *best (other fields copied from
+ * base, which may be NULL) and its time per step to *best_step_us (may be
+ * NULL).
+ *  - 1D candidates: 256- or 512-lane workgroups.
+ *  - 2D candidates: strips of 64/128/256 columns, bands of 4..64 rows, halo
+ *    batches of 2 or 8 rows.
+ * All shapes give identical results, so the choice only affects speed. The
+ * end condition is ignored while timing. Allocates one workspace
+ * (vklb_workspace_bytes) for the duration of the call and synchronizes.
+ * Errors: VKLB_ERR_ARG (steps outside 1..100000, NULL pointers, invalid
+ * problem), VKLB_ERR_OOM, or the last candidate's error if none ran (for
+ * example a state that turns non-physical within the timed steps). */
+vklb_status vklb_tune(const vklb_system* sys, vklb_lattice lat, const vklb_grid* grid, const vklb_speed* lambda,
+                      double omega, const vklb_bc bc[2], const vklb_equilibrium* eq, vklb_precision prec,
+                      const vklb_options* base, const double* U0_host, int steps, void* hip_stream,
+                      vklb_options* best, double* best_step_us);
+
 /* ------------------------------------------------------------------------
  * Serving: a pool of concurrent solves in one device arena.
  *

@@ -529,6 +529,77 @@ vklb_status vklb_set_state(vklb_solver* s, const void* host) {
   return VKLB_OK;
 }
 
+vklb_status vklb_tune(const vklb_system* sys, vklb_lattice lat, const vklb_grid* grid, const vklb_speed* lambda,
+                      double omega, const vklb_bc bc[2], const vklb_equilibrium* eq, vklb_precision prec,
+                      const vklb_options* base, const double* U0_host, int steps, void* hip_stream,
+                      vklb_options* best, double* best_step_us) {
+  if (!U0_host || !best || steps < 1 || steps > 100000) return fail(nullptr, VKLB_ERR_ARG, "vklb_tune: bad arguments");
+  std::string msg;
+  vklb_status vst = validate(sys, lat, grid, lambda, omega, bc, eq, prec, &msg);
+  if (vst != VKLB_OK) return fail(nullptr, vst, msg);
+  vklb_options b0;
+  if (base) b0 = *base;
+  else memset(&b0, 0, sizeof b0);
+  // candidate tile shapes
+  std::vector<vklb_options> cand;
+  if (grid->dim == 1) {
+    for (int w : {256, 512}) {
+      vklb_options o = b0;
+      o.strip_width = w;
+      cand.push_back(o);
+    }
+  } else {
+    const long long nx = grid->n[0], ny = grid->n[1];
+    for (int w : {64, 128, 256}) {
+      if (w > 64 && (nx + w - 1) / w * w - nx >= w / 2) continue;  // mostly idle lanes
+      for (int band : {4, 8, 16, 32, 64}) {
+        if (band > 4 && band / 2 >= ny) continue;
+        for (int halo : {2, 8}) {
+          if (halo > band) continue;
+          vklb_options o = b0;
+          o.strip_width = w;
+          o.band_rows = band;
+          o.halo_rows = halo;
+          cand.push_back(o);
+        }
+      }
+    }
+  }
+  const size_t bytes = vklb_workspace_bytes(sys, lat, grid, prec);
+  void* buf = nullptr;
+  hipError_t e = hipMalloc(&buf, bytes);
+  if (e != hipSuccess) return fail(nullptr, VKLB_ERR_OOM, std::string("vklb_tune: hipMalloc: ") + hipGetErrorString(e));
+  double best_us = INFINITY;
+  vklb_status last = VKLB_OK;
+  for (const vklb_options& o : cand) {
+    vklb_solver* s = nullptr;
+    vklb_status st = vklb_create(sys, lat, grid, lambda, omega, bc, eq, prec, &o, buf, bytes, hip_stream, &s);
+    if (st == VKLB_OK) st = vklb_set_end(s, INFINITY, -1);
+    if (st == VKLB_OK) st = vklb_init(s, U0_host);
+    if (st == VKLB_OK) st = vklb_step(s, std::min(steps, 8));  // warm-up (and graph capture)
+    if (st == VKLB_OK) st = vklb_step(s, steps);
+    double ms = 0.0;
+    if (st == VKLB_OK) st = vklb_last_step_ms(s, &ms);
+    int done = 0;
+    if (st == VKLB_OK) st = vklb_progress(s, nullptr, nullptr, &done);  // non-physical -> error
+    if (st == VKLB_OK && !done && ms > 0.0) {
+      const double us = 1e3 * ms / steps;
+      if (us < best_us) {
+        best_us = us;
+        *best = o;
+      }
+    } else if (st != VKLB_OK) {
+      last = st;
+    }
+    vklb_destroy(s);
+  }
+  (void)hipFree(buf);
+  if (!(best_us < INFINITY))
+    return fail(nullptr, last != VKLB_OK ? last : VKLB_ERR_STATE, "vklb_tune: no candidate ran");
+  if (best_step_us) *best_step_us = best_us;
+  return VKLB_OK;
+}
+
 void vklb_destroy(vklb_solver* s) {
   if (!s) return;
   (void)hipSetDevice(s->device);

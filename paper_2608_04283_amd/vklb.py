@@ -24,7 +24,7 @@ BCS = {"periodic": 0, "zero_gradient": 1, "outflow": 1}
 EXPORTED = ["vklb_workspace_bytes", "vklb_create", "vklb_set_end", "vklb_init", "vklb_init_device", "vklb_step", "vklb_moments",
             "vklb_progress", "vklb_diagnostics", "vklb_state_bytes", "vklb_get_state", "vklb_set_state", "vklb_last_step_ms",
             "vklb_destroy", "vklb_status_str", "vklb_last_error", "vklb_pool_create", "vklb_pool_submit",
-            "vklb_pool_run", "vklb_pool_poll", "vklb_pool_get_stats", "vklb_pool_destroy"]
+            "vklb_pool_run", "vklb_pool_poll", "vklb_pool_get_stats", "vklb_pool_destroy", "vklb_tune"]
 
 
 class VklbError(RuntimeError):
@@ -129,11 +129,14 @@ def lib():
     L.vklb_pool_get_stats.argtypes = [vp, ctypes.POINTER(PoolStats)]
     L.vklb_pool_destroy.argtypes = [vp]
     L.vklb_pool_destroy.restype = None
+    L.vklb_tune.argtypes = [ctypes.POINTER(System), ctypes.c_int, ctypes.POINTER(Grid), ctypes.POINTER(Speed),
+                            ctypes.c_double, ctypes.c_int * 2, ctypes.POINTER(Equilibrium), ctypes.c_int,
+                            ctypes.POINTER(Options), dp, ctypes.c_int, vp, ctypes.POINTER(Options), dp]
     for name in ("vklb_pool_create", "vklb_pool_submit", "vklb_pool_run", "vklb_pool_poll", "vklb_pool_get_stats"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("vklb_create", "vklb_set_end", "vklb_init", "vklb_init_device", "vklb_step", "vklb_moments", "vklb_progress",
                  "vklb_diagnostics",
-                 "vklb_get_state", "vklb_set_state", "vklb_last_step_ms"):
+                 "vklb_get_state", "vklb_set_state", "vklb_last_step_ms", "vklb_tune"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -158,6 +161,25 @@ def _structs(problem):
 def workspace_bytes(problem, precision="fp64") -> int:
     sysd, lat, grid, _, _, _ = _structs(problem)
     return int(lib().vklb_workspace_bytes(ctypes.byref(sysd), lat, ctypes.byref(grid), PRECISIONS[precision]))
+
+
+def tune(problem, precision="fp32", steps=20, basis=0, stream=None):
+    """Fastest tile shape for `problem` (vklb_tune): returns (options dict, us per step)."""
+    import torch
+    L = lib()
+    sysd, lat, grid, speed, eq, bc = _structs(problem)
+    U0 = np.ascontiguousarray(np.asarray(problem.U0, dtype=np.float64).reshape(problem.p, problem.cells))
+    base = Options(int(basis), 0, 0, 0, 0)
+    best = Options()
+    us = ctypes.c_double()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    r = L.vklb_tune(ctypes.byref(sysd), lat, ctypes.byref(grid), ctypes.byref(speed), float(problem.omega), bc,
+                    ctypes.byref(eq), PRECISIONS[precision], ctypes.byref(base), _dp(U0), int(steps),
+                    st.cuda_stream, ctypes.byref(best), ctypes.byref(us))
+    if r != OK:
+        raise VklbError(r, L.vklb_last_error(None).decode())
+    return ({"basis": best.basis, "strip_width": best.strip_width, "band_rows": best.band_rows,
+             "halo_rows": best.halo_rows, "graph_chunk": best.graph_chunk}, us.value)
 
 
 class Solver:

@@ -89,6 +89,19 @@ def test_invalid_basis_rejected(vk, prec, basis):
     assert r == vk.ERR_ARG and "basis" in vk.lib().vklb_last_error(None).decode()
 
 
+def test_tune_rejects_bad_step_count(vk):
+    """Argument checks of vklb_tune come before any device call."""
+    import numpy as np
+    P = I.sod(100)
+    sysd, lat, grid, speed, eq, bc = vk._structs(P)
+    U0 = np.ascontiguousarray(P.U0)
+    best = vk.Options()
+    r = vk.lib().vklb_tune(ctypes.byref(sysd), lat, ctypes.byref(grid), ctypes.byref(speed), P.omega, bc,
+                           ctypes.byref(eq), vk.PRECISIONS["fp32"], None, vk._dp(U0), 0, None, ctypes.byref(best),
+                           None)
+    assert r == vk.ERR_ARG
+
+
 def test_lattice_grid_mismatch_and_dx_dy(vk):
     r, msg = create(vk, I.sod(100), lat=1)
     assert r == vk.ERR_ARG and "lattice" in msg

@@ -112,6 +112,28 @@ def test_tile_shapes_give_identical_results(gpu, prec, basis):
         assert np.array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("dim", [1, 2])
+def test_autotuner_shape_gives_identical_results(gpu, dim):
+    """vklb_tune times the candidate tile shapes and returns the fastest; the
+    chosen shape reproduces the default shape's results bit for bit."""
+    P = rect_quadrants(300, 170, 5, 25) if dim == 2 else I.sod(3000, max_steps=300)
+    opts, us = gpu.tune(P, "fp32", steps=10)
+    print(f"[tune] dim={dim} {opts} {us:.2f} us/step", flush=True)
+    assert us > 0
+    if dim == 1:
+        assert opts["strip_width"] in (256, 512)
+    else:
+        assert opts["strip_width"] in (64, 128, 256) and opts["band_rows"] in (4, 8, 16, 32, 64)
+        assert opts["halo_rows"] in (2, 8)
+    outs = []
+    for kw in ({}, {k: opts[k] for k in ("strip_width", "band_rows", "halo_rows")}):
+        s = gpu.Solver(P, precision="fp32", **kw)
+        s.init()
+        outs.append(s.run())
+        s.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]
+
+
 def test_repeat_runs_and_graph_chunks_identical(gpu):
     P = I.sod(2000, T=0.05)
     res = []
