@@ -83,15 +83,28 @@ typedef struct {
  * boundary carries the post-collision populations of the boundary cell). */
 typedef enum { VKLB_BC_PERIODIC = 0, VKLB_BC_ZERO_GRADIENT = 1 } vklb_bc;
 
-/* Weighted-upwind equilibrium (Sec. 3.1, Sec. 3.4): diffusive weight c and
- * sigmoid sharpness k (k = INFINITY selects the discontinuous split of
- * Sec. 2.2; c = 1/3 (1D) or 1/5 (2D) with k = 0 gives the centered set).
- * The sigmoid normalizer max_j|lambda_j| is the global max over the grid
- * (alpha_local = 0) or the cell's own max for that direction (1). */
+/* Equilibrium distribution set.
+ *  VKLB_EQ_WEIGHTED: the weighted-upwind set (Sec. 3.1 1D, Sec. 3.4 2D) with
+ *    diffusive weight c and sigmoid sharpness k; k = INFINITY gives the step
+ *    weights of the discontinuous split (Sec. 2.2; lambda >= 0 goes to +).
+ *    The sigmoid normalizer max_j|lambda_j| is the global max over the grid
+ *    (alpha_local = 0) or the cell's own max for that direction (1).
+ *  VKLB_EQ_CENTERED: the centered flux set (Sec. 2.2): U/3 +- F/(2 xi) and
+ *    U/3 in 1D, U/5 +- F^(d)/(2 xi) and U/5 in 2D (= weighted with c = 1/3 or
+ *    1/5, k = 0; c and k are ignored). In VKLB_XI_CFL mode nu is read as the
+ *    number eta of the subcharacteristic condition (Sec. 2.3):
+ *    xi = sqrt(3/2) max|lambda| / eta in 1D, sqrt(5/2) max|lambda| / eta in 2D
+ *    (the second moment of the D2Q5 centered set is 2 xi^2/5 per axis).
+ *  VKLB_EQ_DISCONTINUOUS: the discontinuous upwind set (Sec. 2.2):
+ *    F+/xi, U - (F+ - F-)/xi, -F-/xi (= weighted with c = 0, k = INFINITY;
+ *    c and k are ignored); xi by the CFL rule of Sec. 3.2. */
+typedef enum { VKLB_EQ_WEIGHTED = 0, VKLB_EQ_CENTERED = 1, VKLB_EQ_DISCONTINUOUS = 2 } vklb_equilibrium_set;
+
 typedef struct {
   double c;
   double k;
   int alpha_local;
+  int set;           /* vklb_equilibrium_set */
 } vklb_equilibrium;
 
 /* Storage/arithmetic precision of the populations. FP32 keeps FP64 for the

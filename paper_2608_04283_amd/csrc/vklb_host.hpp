@@ -124,8 +124,11 @@ inline vklb_status validate(const vklb_system* sys, vklb_lattice lat, const vklb
   } else {
     return bad(VKLB_ERR_ARG, "unknown speed mode");
   }
-  if (!(eq->c >= 0.0) || !isfinite(eq->c)) return bad(VKLB_ERR_ARG, "c must be >= 0");
-  if (!(eq->k >= 0.0)) return bad(VKLB_ERR_ARG, "k must be >= 0");
+  if (eq->set < VKLB_EQ_WEIGHTED || eq->set > VKLB_EQ_DISCONTINUOUS) return bad(VKLB_ERR_ARG, "unknown equilibrium set");
+  if (eq->set == VKLB_EQ_WEIGHTED) {
+    if (!(eq->c >= 0.0) || !isfinite(eq->c)) return bad(VKLB_ERR_ARG, "c must be >= 0");
+    if (!(eq->k >= 0.0)) return bad(VKLB_ERR_ARG, "k must be >= 0");
+  }
   if (grid->n[0] < 1 || (grid->dim == 2 && grid->n[1] < 1)) return bad(VKLB_ERR_ARG, "empty grid");
   const double dx = (grid->hi[0] - grid->lo[0]) / double(grid->n[0]);
   if (!(dx > 0.0)) return bad(VKLB_ERR_ARG, "hi must exceed lo");
@@ -161,12 +164,22 @@ inline SolveDesc make_desc(char* base, const Layout& L, const vklb_system* sys, 
   d.ph.adv[0] = sys->adv[0];
   d.ph.adv[1] = sys->adv[1];
   d.ph.omega = omega;
-  d.ph.c = eq->c;
-  d.ph.kinf = isinf(eq->k) ? 1 : 0;
-  d.ph.k = d.ph.kinf ? 0.0 : eq->k;
+  // the centered and discontinuous sets are weighted sets with fixed (c, k)
+  double c = eq->c, k = eq->k;
+  if (eq->set == VKLB_EQ_CENTERED) {
+    c = grid->dim == 1 ? 1.0 / 3.0 : 1.0 / 5.0;
+    k = 0.0;
+  } else if (eq->set == VKLB_EQ_DISCONTINUOUS) {
+    c = 0.0;
+    k = INFINITY;
+  }
+  d.ph.c = c;
+  d.ph.kinf = isinf(k) ? 1 : 0;
+  d.ph.k = d.ph.kinf ? 0.0 : k;
   d.ph.alpha_local = eq->alpha_local ? 1 : 0;
   d.dx = (grid->hi[0] - grid->lo[0]) / double(grid->n[0]);
-  d.nu = lambda->nu;
+  // centered set: xi = sqrt(3/2 | 5/2) max|lambda| / eta (subcharacteristic rule)
+  d.nu = eq->set == VKLB_EQ_CENTERED ? lambda->nu / sqrt(grid->dim == 1 ? 1.5 : 2.5) : lambda->nu;
   d.xi_fixed = lambda->xi;
   d.xi_mode = lambda->mode == VKLB_XI_CFL ? 0 : 1;
   d.nx = int(grid->n[0]);

@@ -288,7 +288,7 @@ vklb_status vklb_create(const vklb_system* sys, vklb_lattice lat, const vklb_gri
   else memset(&s->opt, 0, sizeof s->opt);
   s->L = L;
   s->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  if (lambda->mode == VKLB_XI_CFL && eq->c > 0.5 * (1.0 - lambda->nu))
+  if (lambda->mode == VKLB_XI_CFL && eq->set == VKLB_EQ_WEIGHTED && eq->c > 0.5 * (1.0 - lambda->nu))
     s->err = "note: c exceeds (1 - nu)/2, the monotonicity bound of Sec. 4.2";
   hipError_t e = hipGetDevice(&s->device);
   if (e != hipSuccess) {

@@ -67,6 +67,7 @@ class Problem:
     c: float = 0.05
     k: float = 2.0
     alpha_norm: str = "global"    # sigmoid normalized by the global max |lambda| (or "local")
+    eq_set: str = "weighted"      # "weighted" (c, k), "centered" or "discontinuous" (presets)
     bc: tuple = ("zero_gradient", "zero_gradient")
     T: float = math.inf
     max_steps: int = 2**62

@@ -20,6 +20,7 @@ OK, ERR_ARG, ERR_UNSUPPORTED, ERR_OOM, ERR_DEVICE, ERR_NONPHYSICAL, ERR_STATE = 
 SYSTEMS = {"sw": 0, "shallow_water": 0, "euler": 1, "mhd": 2, "linear": 3}
 PRECISIONS = {"fp64": 0, "f64": 0, "fp32": 1, "f32": 1}
 BCS = {"periodic": 0, "zero_gradient": 1, "outflow": 1}
+EQ_SETS = {"weighted": 0, "centered": 1, "discontinuous": 2}
 
 EXPORTED = ["vklb_workspace_bytes", "vklb_create", "vklb_set_end", "vklb_init", "vklb_init_device", "vklb_step", "vklb_moments",
             "vklb_progress", "vklb_diagnostics", "vklb_state_bytes", "vklb_get_state", "vklb_set_state", "vklb_last_step_ms",
@@ -48,7 +49,7 @@ class Speed(ctypes.Structure):
 
 
 class Equilibrium(ctypes.Structure):
-    _fields_ = [("c", ctypes.c_double), ("k", ctypes.c_double), ("alpha_local", ctypes.c_int)]
+    _fields_ = [("c", ctypes.c_double), ("k", ctypes.c_double), ("alpha_local", ctypes.c_int), ("set", ctypes.c_int)]
 
 
 class Options(ctypes.Structure):
@@ -152,7 +153,8 @@ def _structs(problem):
     n = (int(P.n[0]), int(P.n[1]) if P.dim == 2 else 1)
     grid = Grid(P.dim, (ctypes.c_int64 * 2)(*n), (ctypes.c_double * 2)(*P.lo), (ctypes.c_double * 2)(*P.hi))
     speed = Speed(0 if P.xi_mode == "cfl" else 1, P.nu, P.xi)
-    eq = Equilibrium(P.c, P.k, 1 if getattr(P, "alpha_norm", "global") == "local" else 0)
+    eq = Equilibrium(P.c, P.k, 1 if getattr(P, "alpha_norm", "global") == "local" else 0,
+                     EQ_SETS[getattr(P, "eq_set", "weighted")])
     bc = (ctypes.c_int * 2)(BCS[P.bc[0]], BCS[P.bc[1] if len(P.bc) > 1 else P.bc[0]])
     lat = 0 if P.dim == 1 else 1
     return sysd, lat, grid, speed, eq, bc

@@ -5,10 +5,25 @@ import math
 import numpy as np
 
 
+def eq_params(P):
+    """(c, k, nu) the oracle runs for a problem's equilibrium set: the
+    centered set of Sec. 2.2 is c = 1/3 (1D) or 1/5 (2D) with k = 0 and its
+    streaming speed xi = sqrt(3/2 | 5/2) max|lambda| / eta (Sec. 2.3), i.e. the
+    CFL rule with nu = eta / sqrt(3/2 | 5/2); the discontinuous set is c = 0
+    with step weights (k = inf)."""
+    s = getattr(P, "eq_set", "weighted")
+    if s == "centered":
+        return (1.0 / 3.0 if P.dim == 1 else 0.2), 0.0, P.nu / math.sqrt(1.5 if P.dim == 1 else 2.5)
+    if s == "discontinuous":
+        return 0.0, math.inf, P.nu
+    return P.c, P.k, P.nu
+
+
 def oracle_config(O, P, **kw):
+    c, k, nu = eq_params(P)
     d = dict(system=P.system, dim=P.dim, n=P.n if P.dim == 2 else (P.n[0], 1), lo=P.lo, hi=P.hi, g=P.g,
-             gamma=P.gamma, ch_factor=P.ch_factor, adv=P.adv, xi_mode=P.xi_mode, nu=P.nu, xi=P.xi,
-             omega=P.omega, c=P.c, k=P.k, bc=P.bc, T=P.T, max_steps=P.max_steps,
+             gamma=P.gamma, ch_factor=P.ch_factor, adv=P.adv, xi_mode=P.xi_mode, nu=nu, xi=P.xi,
+             omega=P.omega, c=c, k=k, bc=P.bc, T=P.T, max_steps=P.max_steps,
              alpha_norm=getattr(P, "alpha_norm", "global"))
     d.update(kw)
     return O.make_config(**d)

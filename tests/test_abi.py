@@ -71,6 +71,7 @@ def create(vk, P, precision="fp64", **over):
     ({"eq.c": -0.1}, "c must"),
     ({"eq.k": -1.0}, "k must"),
     ({"sys.gamma": 1.0}, "gamma"),
+    ({"eq.set": 3}, "equilibrium set"),
 ])
 def test_invalid_arguments_rejected(vk, over, needle):
     r, msg = create(vk, I.sod(100), **over)
@@ -100,6 +101,26 @@ def test_tune_rejects_bad_step_count(vk):
                            ctypes.byref(eq), vk.PRECISIONS["fp32"], None, vk._dp(U0), 0, None, ctypes.byref(best),
                            None)
     assert r == vk.ERR_ARG
+
+
+def test_size_limits(vk):
+    """Empty grids are invalid; grids beyond 2^31 - 1 cells (32-bit cell
+    indices on the device) are rejected as unsupported; the largest accepted
+    grid reports its workspace size."""
+    P = I.sod(100)
+    for n in ((0,), (-5,)):
+        assert vk.workspace_bytes(P.with_(n=n), "fp32") == 0
+        r, msg = create(vk, P.with_(n=n))
+        assert r == vk.ERR_ARG and "empty" in msg
+    Q = I.quadrants(16, steps=1)
+    big = Q.with_(n=(65536, 32768), hi=(2.0, 1.0))   # 2^31 cells: one too many
+    assert vk.workspace_bytes(big, "fp32") == 0
+    r, msg = create(vk, big)
+    assert r == vk.ERR_UNSUPPORTED and "too large" in msg
+    ok = Q.with_(n=(65535, 32768), hi=(65535 / 32768, 1.0))  # < 2^31 cells
+    b = vk.workspace_bytes(ok, "fp32")
+    cells = 65535 * 32768
+    assert b >= 2 * 6 * 4 * cells * 4   # two buffers of (Q + 1) * p FP32 planes
 
 
 def test_lattice_grid_mismatch_and_dx_dy(vk):

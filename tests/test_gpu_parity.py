@@ -52,6 +52,9 @@ CASES = {
     "euler1d_sod_local_alpha_fp64": (lambda: I.sod(1500, alpha_norm="local"), "fp64", {}),
     "euler1d_sod_discontinuous_fp64": (lambda: I.sod(1500, c=0.0, k=math.inf, nu=0.5), "fp64", {}),
     "euler1d_sod_centered_fp64": (lambda: I.sod(1500, c=1.0 / 3.0, k=0.0, nu=0.9 / math.sqrt(1.5)), "fp64", {}),
+    "euler1d_sod_centered_preset_fp64": (lambda: I.sod(1500, eq_set="centered", nu=0.9), "fp64", {}),
+    "euler1d_sod_discontinuous_preset_fp64": (lambda: I.sod(1500, eq_set="discontinuous", nu=0.5), "fp64", {}),
+    "sw1d_dambreak_centered_preset_fp32": (lambda: I.dam_break(1000, eq_set="centered", nu=0.9), "fp32", {}),
     "mhd1d_briowu_fp64": (lambda: I.brio_wu(700), "fp64", {}),
     "mhd1d_briowu_fp32": (lambda: I.brio_wu(700), "fp32", {}),
     "sw1d_riemann_omega13_fp64": (lambda: I.random_riemann("sw", 1, 777, seed=5, omega=1.3, max_steps=300,
@@ -64,6 +67,10 @@ CASES = {
     "euler2d_rect_mixed_bc_fp32": (lambda: rect_quadrants(300, 170, 4, 50, bc=("periodic", "zero_gradient")),
                                    "fp32", {}),
     "euler2d_quad_omega15_fp64": (lambda: I.quadrants(130, seed=2, steps=40, omega=1.5, nu=0.3), "fp64", {}),
+    "euler2d_quad_centered_preset_fp64": (lambda: I.quadrants(130, seed=2, steps=40, eq_set="centered", nu=0.8),
+                                          "fp64", {}),
+    "euler2d_quad_discontinuous_preset_fp32": (lambda: I.quadrants(130, seed=2, steps=40, eq_set="discontinuous",
+                                                                   nu=0.3), "fp32", {}),
     "mhd2d_ot_fp64": (lambda: I.orszag_tang(96, steps=60), "fp64", {}),
     "mhd2d_ot_fp32": (lambda: I.orszag_tang(96, steps=60), "fp32", {}),
     "sw2d_riemann_fp64": (lambda: I.random_riemann("sw", 2, 130, seed=7, max_steps=80), "fp64", {}),
@@ -110,6 +117,21 @@ def test_tile_shapes_give_identical_results(gpu, prec, basis):
         s.close()
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_centered_preset_equals_its_weighted_parameters(gpu, dim):
+    """VKLB_EQ_CENTERED is the weighted set with c = 1/3 (1/5), k = 0 and the
+    CFL number eta / sqrt(3/2) (eta / sqrt(5/2)): the same bits."""
+    base = I.sod(1200, T=0.05) if dim == 1 else I.quadrants(96, seed=4, steps=30)
+    eta, cc, f = 0.85, (1.0 / 3.0 if dim == 1 else 0.2), (1.5 if dim == 1 else 2.5)
+    outs = []
+    for P in (base.with_(eq_set="centered", nu=eta), base.with_(c=cc, k=0.0, nu=eta / math.sqrt(f))):
+        s = gpu.Solver(P, precision="fp64")
+        s.init()
+        outs.append(s.run())
+        s.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]
 
 
 @pytest.mark.parametrize("dim", [1, 2])
