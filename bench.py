@@ -47,12 +47,19 @@ def alg_bytes_per_cell_step(P, prec):
     return 2 * P.Q * P.p * (4 if prec == "fp32" else 8)
 
 
+# Files that define the step kernels and their launch parameters (tile
+# shapes, bands, halo batches): a change to any of them makes earlier byte
+# counts stale. The runtime, the pool and the host cell check are not among
+# them.
+KERNEL_SOURCES = ("vklb_cell.hpp", "vklb_kernels.hpp", "vklb_launch.hpp", "vklb_host.hpp", "vklb_system.inc",
+                  "k_sw.hip", "k_euler.hip", "k_mhd.hip", "k_linear.hip")
+
+
 def kernel_sources_sha():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2608_04283_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hpp", ".hip", ".inc")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 

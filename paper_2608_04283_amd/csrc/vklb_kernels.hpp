@@ -123,11 +123,30 @@ __device__ inline int xcd_remap(int b, int nb) {
 }
 
 
-template <class T>
-__device__ inline T wave_max(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
+// Max over the 64 lanes of a wavefront, in every lane, with DPP row
+// operations (quad permutes, row mirrors, the row broadcasts of lanes 15 and
+// 31) and no LDS round trip; the result is read from lane 63. Every lane of
+// the wavefront must be active.
+__device__ inline unsigned wave_umax(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Max of non-negative doubles (negatives and NaN count as 0): the IEEE bit
+// patterns of non-negative doubles order like unsigned integers, so the max
+// is the max high word, then the max low word among the lanes holding it.
+__device__ inline double wave_max(double v) {
+  v = v >= 0.0 ? v : 0.0;
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned hi = unsigned(b >> 32), lo = unsigned(b);
+  const unsigned hm = wave_umax(hi);
+  const unsigned lm = wave_umax(hi == hm ? lo : 0u);
+  return __longlong_as_double((long long)(((unsigned long long)hm << 32) | lm));
 }
 
 // Block max of (a, b) into lane 0 of wave 0; `red` needs 2 * (blockDim/64) doubles.
