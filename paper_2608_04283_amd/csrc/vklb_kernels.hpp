@@ -161,7 +161,8 @@ __device__ inline void block_max2(double& a, double& b, double* red) {
   }
 }
 
-// Block max of (a, b) broadcast to every lane; `red` needs 2 * (blockDim/64) + 2 doubles.
+// Block max of (a, b) broadcast to every lane; `red` needs 2 * (blockDim/64)
+// doubles and is not written again by this workgroup (no trailing barrier).
 __device__ inline void block_max2_all(double& a, double& b, double* red) {
   a = wave_max(a);
   b = wave_max(b);
@@ -169,10 +170,10 @@ __device__ inline void block_max2_all(double& a, double& b, double* red) {
   if (lane == 0) { red[wid] = a; red[nw + wid] = b; }
   __syncthreads();
   for (int w = 0; w < nw; ++w) { a = fmax(a, red[w]); b = fmax(b, red[nw + w]); }
-  __syncthreads();
 }
 
 // Reduce the partials of the previous launch and derive the step scalars.
+// `red` is this reduction's own LDS scratch (2 * blockDim/64 doubles).
 __device__ inline Step begin_step(const SolveDesc& sd, double* red) {
   const double* pl = sd.part + (long long)sd.par * 2 * sd.nblocks;
   const double* pc = pl + sd.nblocks;
@@ -372,7 +373,7 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
   using K = Kern<KIND, 1, T, BASIS>;
   constexpr bool DELTA = K::DELTA;
   constexpr int P = K::P, Q = 3, TW = B - 2;
-  __shared__ double red[2 * (B / 64) + 2];
+  __shared__ double red[2 * (B / 64) + 2], red_end[2 * (B / 64) + 2];
   const int N = sd.nx;
   const int tid = threadIdx.x;
   const int x = tile * TW - 1 + tid;
@@ -419,7 +420,7 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
     }
     K::new_state(sd, Un, x, n + 1, lam, cfm);
   }
-  block_max2(lam, cfm, red);
+  block_max2(lam, cfm, red_end);
   end_step(sd, S, tile, lam, cfm);
 }
 
@@ -442,7 +443,7 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   using K = Kern<KIND, 2, T, BASIS>;
   constexpr bool DELTA = K::DELTA;
   constexpr int P = K::P, Q = 5, REST = 2;
-  __shared__ double red[2 * (W / 64) + 2];
+  __shared__ double red[2 * (W / 64) + 2], red_end[2 * (W / 64) + 2];
   const int nx = sd.nx, ny = sd.ny, H = sd.band;
   const int nsx = (nx + W - 1) / W;
   const int sx = tile % nsx, sy = tile / nsx;
@@ -606,7 +607,7 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   if (PARTIAL) K::template relax_one<1>(fraw[REST], fraw[4], false, sd.ph, ixi, Lam, ch, fs[4]);
   else K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
   if (x < nx) finish(y1);
-  block_max2(lam, cfm, red);
+  block_max2(lam, cfm, red_end);
   end_step(sd, S, tile, lam, cfm);
 }
 
