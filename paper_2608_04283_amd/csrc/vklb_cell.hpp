@@ -318,9 +318,14 @@ struct Cell<K_MHD, DIM, S> {
     y[6] = w.bz * bp + w.by * bq;
   }
 
-  // Directions whose MHD speeds nearly coincide: the fast and slow speeds
-  // nearly meet (c_f^2 - c_s^2 small) or the transverse or normal field nearly
-  // vanishes. The FP32 split computes their eigenstructure in FP64.
+  // Directions near the triple point, where the fast and slow speeds nearly
+  // meet (c_f^2 - c_s^2 = disc small: transverse field -> 0 and a^2 -> b_n^2
+  // together): the FP32 split computes their eigenstructure in FP64. Near the
+  // other coincidences (transverse field -> 0 alone, where the fast or slow
+  // speed meets the Alfven speed, or normal field -> 0) the FP32 closed form
+  // with the Roe-Balsara normalization stays at FP32 rounding of the FP64
+  // split at every distance, so those stay in FP32; near the triple point it
+  // loses up to ~1e-6 without FP64.
   __host__ __device__ static bool near_degenerate(int d, const S* U, S gamma) {
     const S rho = U[0];
     const S a2 = qdiv(gamma * pressure(U, gamma), rho);
@@ -328,7 +333,7 @@ struct Cell<K_MHD, DIM, S> {
     const S bt2 = qdiv(U[5] * U[5] + U[6] * U[6] + U[7] * U[7], rho) - bn2;
     const S tot = a2 + bn2 + bt2;
     const S disc2 = sq(a2 - bn2) + bt2 * (S(2) * a2 + S(2) * bn2 + bt2);
-    return disc2 < S(1e-4) * tot * tot || bt2 < S(1e-4) * tot || bn2 < S(1e-4) * tot;
+    return disc2 < S(1e-4) * tot * tot;
   }
 
   // Wave speeds and Roe-Balsara normalization of one direction, in precision R.

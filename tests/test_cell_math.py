@@ -142,10 +142,12 @@ def test_feq_and_speeds_match_oracle(oracle, cc, system, dim):
             assert abs(lam[0] - lam_o) < 1e-13 * lam_o
 
 
-@pytest.mark.parametrize("deg", [None, "bt0", "bt_small", "triple", "bx0"])
+@pytest.mark.parametrize("deg", [None, "bt0", "bt_small", "triple", "triple_near", "bx0"])
 def test_mhd_split_fp32_at_degenerate_states(oracle, cc, deg):
-    """The FP32 MHD split (FP64 only near coinciding speeds) stays within
-    1e-6 of the oracle at and near degenerate states."""
+    """The FP32 MHD split (FP64 eigenstructure only near the triple point,
+    where the fast and slow speeds meet) stays within 1e-6 of the oracle at
+    and near every degenerate state: transverse field zero or tiny (fast or
+    slow = Alfven), the triple point, normal field zero."""
     O = oracle
     rng = np.random.default_rng(25)
     for dim in (1, 2):

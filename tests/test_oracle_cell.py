@@ -32,6 +32,9 @@ def rand_state(system, dim, rng, degenerate=None):
     elif degenerate == "triple":     # b_t = 0 and a^2 = b_x^2: three speeds coincide
         B[1:] = 0.0
         B[0] = math.sqrt(2.0 * p)    # gamma = 2 -> a^2 = 2p/rho = Bx^2/rho
+    elif degenerate == "triple_near":  # near the triple point, inside the FP32 path's FP64 band
+        B[1:] *= 3e-4
+        B[0] = math.sqrt(2.0 * p) * (1.0 + 3e-4)
     elif degenerate == "bx0":        # normal field -> 0: five eigenvalues equal u
         B[0] = 0.0
     psi = rng.uniform(-0.1, 0.1)
