@@ -108,8 +108,9 @@ typedef struct {
 } vklb_equilibrium;
 
 /* Storage/arithmetic precision of the populations. FP32 keeps FP64 for the
- * MHD split of directions whose characteristic speeds nearly coincide, for
- * the time t, the streaming speed and the diagnostics. */
+ * MHD eigenstructure of directions near the triple point (fast and slow
+ * speeds nearly equal), for the time t, the streaming speed and the
+ * diagnostics. */
 typedef enum { VKLB_FP64 = 0, VKLB_FP32 = 1 } vklb_precision;
 
 typedef struct {
