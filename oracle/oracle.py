@@ -22,11 +22,11 @@ _SRC = os.path.join(_HERE, "vklb_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle_vklb.so")
 
 SW, EULER, MHD, LINEAR = 0, 1, 2, 3
-PERIODIC, ZERO_GRADIENT = 0, 1
+PERIODIC, ZERO_GRADIENT, CHARACTERISTIC = 0, 1, 2
 XI_CFL, XI_FIXED = 0, 1
 
 _SYS = {"sw": SW, "shallow_water": SW, "euler": EULER, "mhd": MHD, "linear": LINEAR}
-_BC = {"periodic": PERIODIC, "zero_gradient": ZERO_GRADIENT, "outflow": ZERO_GRADIENT}
+_BC = {"periodic": PERIODIC, "zero_gradient": ZERO_GRADIENT, "outflow": ZERO_GRADIENT, "characteristic": CHARACTERISTIC}
 
 
 class OrConfig(ctypes.Structure):
@@ -102,6 +102,8 @@ def lib():
         L.or_global_lambda.restype = ctypes.c_double
         L.or_fast_speed.argtypes = [cp, ctypes.c_int, dp]
         L.or_fast_speed.restype = ctypes.c_double
+        L.or_char.argtypes = [cp, dp, dp, ctypes.c_double, ctypes.c_int, dp]
+        L.or_char.restype = ctypes.c_int
         L.or_run.argtypes = [cp, dp, dp, dp, dp, ctypes.c_int64, ctypes.POINTER(OrResult)]
         L.or_run.restype = ctypes.c_int
         _lib = L
@@ -227,6 +229,17 @@ def fast_speed(cf: OrConfig, d: int, U):
     p = lib().or_nvars(cf.kind, cf.dim)
     U = _vec(U, p)
     return lib().or_fast_speed(ctypes.byref(cf), d, _dp(U))
+
+
+def char_correction(cf: OrConfig, Ub, dU, ch: float = 0.0, right: bool = True):
+    """P (Lambda dW)' of the characteristic boundary (Sec. 3.3) at a node with
+    state Ub for the one-sided increment dU: U_b^{n+1} = U_b - out / xi."""
+    p = lib().or_nvars(cf.kind, cf.dim)
+    Ub, dU = _vec(Ub, p), _vec(dU, p)
+    out = np.zeros(p)
+    if lib().or_char(ctypes.byref(cf), _dp(Ub), _dp(dU), ch, 1 if right else 0, _dp(out)) != 0:
+        raise RuntimeError("oracle char_correction failed")
+    return out
 
 
 def run(cf: OrConfig, U0, want_f: bool = False, want_xi: bool = False) -> dict:

@@ -39,7 +39,7 @@ namespace {
 using cd = std::complex<double>;
 
 enum { SYS_SW = 0, SYS_EULER = 1, SYS_MHD = 2, SYS_LINEAR = 3 };
-enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1 };
+enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1, BC_CHARACTERISTIC = 2 };
 enum { XI_CFL = 0, XI_FIXED = 1 };
 
 constexpr int PMAX = 9;
@@ -64,7 +64,7 @@ typedef struct {
   double k;          // sigmoid sharpness; +inf selects the discontinuous split
   int alpha_norm;    // 0: lambda_max of the sigmoid is the global max |lambda|
                      //    (the CFL speed nu*xi); 1: max over the cell's own eigenvalues
-  int bc[2];         // per axis: BC_PERIODIC or BC_ZERO_GRADIENT
+  int bc[2];         // per axis: BC_PERIODIC, BC_ZERO_GRADIENT or BC_CHARACTERISTIC (1D)
   double T;          // end time (+inf: none)
   int64_t max_steps; // step limit
   double cluster_tol;// relative eigenvalue clustering tolerance
@@ -386,6 +386,55 @@ bool split(const or_config& cf, int d, const double* U, double ch, double Lam, d
   return true;
 }
 
+// Characteristic (non-reflecting) boundary correction of Sec. 3.3 at a
+// boundary node b: with A(U_b) = P Lambda P^{-1}, the characteristic
+// variables W = P^{-1} U advance by dW^j/dt = -(lambda^j dW^j/dx)' where the
+// product is kept for outgoing waves (lambda^j > 0 at the right boundary,
+// < 0 at the left) and zeroed for incoming ones. dW/dx is the first-order
+// one-sided difference towards the interior, linearized about b (a reading:
+// the paper does not state the difference), dW = P^{-1} dU with dU = U_b -
+// U_{b-1} (right) or U_{b+1} - U_b (left). Returns P (Lambda dW)' in out, so
+// that U_b^{n+1} = U_b - out / xi (dt / dx = 1 / xi).
+bool char_correction(const or_config& cf, const double* Ub, const double* dU, double ch, int right, double* out) {
+  const int p = nvars(cf.kind, cf.dim);
+  double lam[PMAX], A[PMAX * PMAX];
+  eigenvalues(cf, 0, Ub, ch, lam);
+  jacobian(cf, 0, Ub, ch, A);
+  double lmax = 0.0;
+  for (int j = 0; j < p; ++j) lmax = std::max(lmax, std::fabs(lam[j]));
+  double R[PMAX * PMAX], g[PMAX];
+  int j0 = 0;
+  while (j0 < p) {
+    int j1 = j0 + 1;
+    while (j1 < p && lam[j1] - lam[j1 - 1] <= cf.cluster_tol * lmax) ++j1;
+    const int m = j1 - j0;
+    double mean = 0.0;
+    for (int j = j0; j < j1; ++j) mean += lam[j];
+    mean /= m;
+    double M[PMAX * PMAX];
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < p; ++j) M[i * p + j] = A[i * p + j] - (i == j ? mean : 0.0);
+    double vecs[PMAX * PMAX];
+    nullspace(p, M, m, vecs);
+    const bool outgoing = right ? mean > 0.0 : mean < 0.0;
+    for (int r = 0; r < m; ++r) {
+      for (int i = 0; i < p; ++i) R[i * p + (j0 + r)] = vecs[r * p + i];
+      g[j0 + r] = outgoing ? mean : 0.0;
+    }
+    j0 = j1;
+  }
+  double w[PMAX];
+  if (!lu_solve(p, R, dU, w)) return false;
+  for (int i = 0; i < p; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < p; ++j) s += g[j] * w[j] * R[i * p + j];
+    out[i] = s;
+  }
+  for (int i = 0; i < p; ++i)
+    if (!std::isfinite(out[i])) return false;
+  return true;
+}
+
 // Weighted-upwind equilibrium set, populations ordered as the paper's
 // velocities: 1D (+xi, 0, -xi) (Sec. 3.1); 2D (+x, -x, 0, +y, -y) (Sec. 3.4).
 bool feq(const or_config& cf, const double* U, double xi, double ch, double Lam, double* out) {
@@ -461,7 +510,7 @@ int64_t src_index(int64_t i, int m, int64_t n, int bc) {
   int64_t s = i - m;
   if (s >= 0 && s < n) return s;
   if (bc == BC_PERIODIC) return (s + n) % n;
-  return i;  // zero gradient: the boundary cell itself
+  return i;  // zero gradient: the boundary cell itself (characteristic: replaced afterwards)
 }
 
 // Neumaier compensated sum.
@@ -593,6 +642,12 @@ double or_global_lambda(const or_config* cfp, const double* U, int64_t ncell, do
 
 double or_fast_speed(const or_config* cf, int d, const double* U) { return mhd_cf(*cf, d, U); }
 
+// P (Lambda dW)' of the characteristic boundary at a node with state Ub for
+// the increment dU (right = 1: right boundary); 0 on success.
+int or_char(const or_config* cf, const double* Ub, const double* dU, double ch, int right, double* out) {
+  return char_correction(*cf, Ub, dU, ch, right, out) ? 0 : 1;
+}
+
 // Full run following the flow chart of Sec. 3.5.
 //   U0:   initial conserved state, SoA [var][cell], cell = j*nx + i.
 //   Uout: final conserved state, same layout.
@@ -677,6 +732,28 @@ int or_run(const or_config* cfp, const double* U0, double* Uout, double* fout, d
             R.fn[(size_t(q) * p + v) * N + c] = R.fs[(size_t(q) * p + v) * N + sc];
         }
       }
+    // Characteristic boundaries (Sec. 3.3, 1D): the boundary node's
+    // populations are replaced by f^eq(U_b^{n+1}), U_b^{n+1} = U_b^n - P
+    // (Lambda dW)' / xi, from U^n (R.U still holds it); the equilibrium uses
+    // this step's xi and Lambda (a reading: the paper writes f^eq(U) without
+    // naming the streaming speed of the new time level).
+    if (R.dim == 1 && cf.bc[0] == BC_CHARACTERISTIC && nx >= 2) {
+      for (int side = 0; side < 2; ++side) {
+        const int64_t b = side == 0 ? 0 : nx - 1, nb = side == 0 ? 1 : nx - 2;
+        double Ub[PMAX], Un[PMAX], dU[PMAX], corr[PMAX], fe[5 * PMAX];
+        for (int v = 0; v < p; ++v) {
+          Ub[v] = R.U[size_t(v) * N + b];
+          Un[v] = R.U[size_t(v) * N + nb];
+          dU[v] = side == 1 ? Ub[v] - Un[v] : Un[v] - Ub[v];
+        }
+        if (!char_correction(cf, Ub, dU, ch, side, corr)) { sbad |= 1; break; }
+        for (int v = 0; v < p; ++v) Ub[v] -= corr[v] / xi;
+        if (!feq(cf, Ub, xi, ch, lam, fe)) { sbad |= 1; break; }
+        for (int q = 0; q < Q; ++q)
+          for (int v = 0; v < p; ++v) R.fn[(size_t(q) * p + v) * N + b] = fe[q * p + v];
+      }
+      if (sbad) { res->status = 2; res->fail_step = n; break; }
+    }
     std::swap(R.f, R.fn);
     t = last ? cf.T : t + dt;
     n += 1;

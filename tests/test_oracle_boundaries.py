@@ -1,0 +1,131 @@
+"""Pins of the oracle's characteristic (non-reflecting) boundaries of
+Sec. 3.3 (no GPU): the correction is the matrix function (A +- |A|)/2 applied
+to the one-sided increment, reduces to first-order upwinding at a scalar
+outflow boundary and to no change at an inflow one, and lets an acoustic
+pulse leave the domain without a reflection.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from paper_2608_04283_amd import inputs as I
+from test_oracle_cell import cfg, ch_for, rand_state
+from test_oracle_scheme import cfg_of
+
+
+@pytest.mark.parametrize("system", ["sw", "euler", "mhd"])
+@pytest.mark.parametrize("right", [True, False])
+def test_char_correction_is_half_a_plus_abs_a(oracle, system, right):
+    """P (Lambda dW)' with outgoing waves only equals (A + |A|)/2 dU at the
+    right boundary and (A - |A|)/2 dU at the left one; |A| = sqrtm(A^2) is
+    taken without eigenvectors."""
+    O = oracle
+    rng = np.random.default_rng(41)
+    cf = cfg(O, system, 1)
+    for _ in range(10):
+        U = rand_state(system, 1, rng)
+        ch = ch_for(O, cf, U)
+        dU = rng.normal(size=U.shape) * 0.1
+        A = O.jacobian(cf, 0, U, ch)
+        absA = np.real(scipy.linalg.sqrtm(A @ A))
+        ref = 0.5 * (A + absA) @ dU if right else 0.5 * (A - absA) @ dU
+        got = O.char_correction(cf, U, dU, ch, right=right)
+        assert np.max(np.abs(got - ref)) < 1e-9 * (np.max(np.abs(A)) * np.max(np.abs(dU)) + 1e-30)
+
+
+def linear1d(n, a, xi, steps, bc):
+    P = I.Problem(name="linear1d", system="linear", dim=1, n=(n,), adv=(a, 0.0), xi_mode="fixed", xi=xi,
+                  bc=(bc, bc), max_steps=steps)
+    x = I.cell_centres(n, 0.0, 1.0)
+    return P.with_(U0=(1.0 + 0.5 * np.sin(2 * np.pi * x) + x).reshape(1, -1))
+
+
+@pytest.mark.parametrize("a", [0.7, -0.7])
+def test_scalar_characteristic_boundary_is_upwind(oracle, a):
+    """Scalar advection, one step: at the outflow boundary U_b^{n+1} =
+    U_b - (a / xi) (one-sided difference), at the inflow boundary U_b is kept."""
+    O = oracle
+    P = linear1d(40, a, 2.0, 1, "characteristic")
+    r = O.run(cfg_of(O, P), P.U0)
+    U0, U1 = P.U0[0], r["U"][0]
+    xi = 2.0
+    if a > 0:
+        assert U1[-1] == pytest.approx(U0[-1] - a / xi * (U0[-1] - U0[-2]), abs=1e-14)
+        assert U1[0] == pytest.approx(U0[0], abs=1e-14)
+    else:
+        assert U1[0] == pytest.approx(U0[0] - a / xi * (U0[1] - U0[0]), abs=1e-14)
+        assert U1[-1] == pytest.approx(U0[-1], abs=1e-14)
+
+
+def acoustic_pulse(n, lo, hi, T):
+    """Right-running acoustic pulse (Euler, gamma = 1.4) on a quiescent gas:
+    p = 1 + eps g, rho = 1 + eps g / c^2, u = eps g / (rho c) with a Gaussian g
+    centred at x = 0.6. nu = 0.5: near rest the weighted split's Jacobian
+    difference J+ - J- reaches 1.39 Lambda (the weights vary with U), which
+    the explicit update tolerates up to nu ~ 0.65 (see the stability test)."""
+    P = I.Problem(name="pulse", system="euler", dim=1, n=(n,), lo=(lo, 0.0), hi=(hi, 1.0), gamma=1.4, nu=0.5,
+                  T=T, bc=("characteristic", "characteristic"))
+    x = I.cell_centres(n, lo, hi)
+    eps, c = 1e-3, math.sqrt(1.4)
+    g = np.exp(-((x - 0.6) / 0.05) ** 2)
+    rho = 1.0 + eps * g / c ** 2
+    return P.with_(U0=I.euler_state(rho, eps * g / c, 1.0 + eps * g, 1.4))
+
+
+def test_acoustic_pulse_leaves_without_reflection(oracle):
+    """After the pulse has crossed the right boundary (t = 0.6, the pulse
+    travels ~0.71), the state on [0, 1] matches the run on [0, 3] (no
+    boundary reached) to a small fraction of the pulse amplitude, while a
+    periodic domain brings the whole pulse back."""
+    O = oracle
+    T = 0.6
+    n = 400
+    small = acoustic_pulse(n, 0.0, 1.0, T)
+    big = acoustic_pulse(3 * n, 0.0, 3.0, T).with_(bc=("zero_gradient", "zero_gradient"))
+    rs = O.run(cfg_of(O, small), small.U0)
+    rb = O.run(cfg_of(O, big), big.U0)
+    assert rs["status"] == 0 and rb["status"] == 0
+    p_s = (0.4) * (rs["U"][2] - 0.5 * rs["U"][1] ** 2 / rs["U"][0])
+    p_b = (0.4) * (rb["U"][2] - 0.5 * rb["U"][1] ** 2 / rb["U"][0])[:n]
+    err = np.max(np.abs(p_s - p_b))
+    per = small.with_(bc=("periodic", "periodic"))
+    rp = O.run(cfg_of(O, per), per.U0)
+    p_p = (0.4) * (rp["U"][2] - 0.5 * rp["U"][1] ** 2 / rp["U"][0])
+    err_p = np.max(np.abs(p_p - p_b))
+    print(f"[pulse] characteristic {err:.2e}, periodic {err_p:.2e} (amplitude 1e-3)")
+    assert err < 5e-5 and err < 0.1 * err_p
+
+
+def test_weighted_split_viscosity_at_rest_limits_nu(oracle):
+    """Gas at rest (Euler, u = 0): with the weights frozen, J+ - J- has
+    eigenvalues tanh(k/2) |lambda| (here 0, 0.90, 0.90); the weights' own
+    dependence on U raises the largest to about 1.39 Lambda. The explicit
+    update keeps the diffusion coefficient c + max eig / (2 xi) below 1/2
+    only for nu below ~0.65: a constant state with 1e-9 noise grows at
+    nu = 0.9 and stays put at nu = 0.5."""
+    O = oracle
+    cf = O.make_config(system="euler", dim=1, n=(8, 1), gamma=1.4, k=2.0)
+    U = I.euler_state(np.array([1.0]), 0.0, 1.0, 1.4)[:, 0]
+    Lam = math.sqrt(1.4)
+    h = 1e-6
+    J = np.zeros((3, 3))
+    for j in range(3):
+        e = np.zeros(3)
+        e[j] = h
+        J[:, j] = (O.split(cf, 0, U + e, 0.0, lam=Lam)[0] - O.split(cf, 0, U - e, 0.0, lam=Lam)[0]) / (2 * h)
+    A = O.jacobian(cf, 0, U, 0.0)
+    visc = np.sort(np.linalg.eigvals(2 * J - A).real)
+    assert visc[-1] / Lam == pytest.approx(1.3879, rel=2e-3)
+    assert np.all(visc > 0)
+    nu_max = (0.5 - 0.05) * 2 * Lam / visc[-1]
+    assert 0.6 < nu_max < 0.7
+    P = acoustic_pulse(200, 0.0, 1.0, math.inf).with_(bc=("periodic", "periodic"), max_steps=200)
+    rng = np.random.default_rng(0)
+    U0 = np.repeat(U.reshape(3, 1), 200, axis=1) * (1 + 1e-9 * rng.normal(size=(3, 200)))
+    growth = {}
+    for nu in (0.9, 0.5):
+        r = O.run(cfg_of(O, P.with_(nu=nu)), U0)
+        growth[nu] = np.abs(r["U"] - U0.mean(axis=1, keepdims=True)).max()
+    assert growth[0.9] > 1e-4 and growth[0.5] < 1e-8
