@@ -125,6 +125,14 @@ struct Cell;
 template <int DIM, class S>
 struct Cell<K_LINEAR, DIM, S> {
   static constexpr int P = 1;
+  // Characteristic boundary of Sec. 3.3 (1D): out = g(a) dU with g(a) = a for
+  // an outgoing wave (a > 0 at the right boundary, a < 0 at the left), else 0.
+  __host__ __device__ static bool char_correction(const S* Ub, const S* dU, const Phys& ph, bool right, S* out) {
+    (void)Ub;
+    const S a = S(ph.adv[0]);
+    out[0] = (right ? a > S(0) : a < S(0)) ? a * dU[0] : S(0);
+    return true;
+  }
   __host__ __device__ static void speeds(const S* U, const Phys& ph, S* lam, S* cfm) {
     S m = S(0);
     for (int d = 0; d < DIM; ++d) m = fmax(m, fabs(S(ph.adv[d])));
@@ -146,6 +154,23 @@ struct Cell<K_LINEAR, DIM, S> {
 template <int DIM, class S>
 struct Cell<K_SW, DIM, S> {
   static constexpr int P = DIM + 1;
+  // Characteristic boundary of Sec. 3.3 (1D): out = sum_j g(lambda_j) (l_j . dU) r_j
+  // over u -+ c, with r = (1, u -+ c), l = (+-(u +- c), -+1) / (2c) and g the
+  // speed for outgoing waves, 0 for incoming ones.
+  __host__ __device__ static bool char_correction(const S* Ub, const S* dU, const Phys& ph, bool right, S* out) {
+    const S h = Ub[0];
+    const S u = qdiv(Ub[1], h);
+    const S c = qsqrt(S(ph.g) * h);
+    const S l1 = u - c, l2 = u + c;
+    const S i2c = qrcp(S(2) * c);
+    const S w1 = ((u + c) * dU[0] - dU[1]) * i2c;
+    const S w2 = (dU[1] - (u - c) * dU[0]) * i2c;
+    const S g1 = (right ? l1 > S(0) : l1 < S(0)) ? l1 : S(0);
+    const S g2 = (right ? l2 > S(0) : l2 < S(0)) ? l2 : S(0);
+    out[0] = g1 * w1 + g2 * w2;
+    out[1] = g1 * w1 * l1 + g2 * w2 * l2;
+    return isfinite(out[0]) && isfinite(out[1]);
+  }
   __host__ __device__ static void speeds(const S* U, const Phys& ph, S* lam, S* cfm) {
     S h = U[0];
     S c = qsqrt(S(ph.g) * h);
@@ -183,6 +208,33 @@ struct Cell<K_SW, DIM, S> {
 template <int DIM, class S>
 struct Cell<K_EULER, DIM, S> {
   static constexpr int P = DIM + 2;
+  // Characteristic boundary of Sec. 3.3 (1D): out = sum_j g(lambda_j) (l_j . dU) r_j
+  // over u - a, u, u + a with the textbook eigenvectors r = (1, u -+ a, H -+ ua),
+  // (1, u, u^2/2) and left eigenvectors (b1 = (gamma-1)/a^2, b2 = b1 u^2/2)
+  // l_1,3 = (b2 +- u/a, -(b1 u +- 1/a), b1)/2, l_2 = (1 - b2, b1 u, -b1);
+  // g is the speed for outgoing waves, 0 for incoming ones.
+  __host__ __device__ static bool char_correction(const S* Ub, const S* dU, const Phys& ph, bool right, S* out) {
+    const S gamma = S(ph.gamma);
+    const S rho = Ub[0];
+    const S u = qdiv(Ub[1], rho);
+    const S E = Ub[2];
+    const S p = (gamma - S(1)) * (E - S(0.5) * rho * u * u);
+    const S a = qsqrt(qdiv(gamma * p, rho));
+    const S H = qdiv(E + p, rho);
+    const S ia = qrcp(a);
+    const S b1 = (gamma - S(1)) * ia * ia, b2 = S(0.5) * b1 * u * u;
+    const S w1 = S(0.5) * ((b2 + u * ia) * dU[0] - (b1 * u + ia) * dU[1] + b1 * dU[2]);
+    const S w2 = (S(1) - b2) * dU[0] + b1 * u * dU[1] - b1 * dU[2];
+    const S w3 = S(0.5) * ((b2 - u * ia) * dU[0] - (b1 * u - ia) * dU[1] + b1 * dU[2]);
+    const S lam[3] = {u - a, u, u + a};
+    S g[3];
+    for (int j = 0; j < 3; ++j) g[j] = (right ? lam[j] > S(0) : lam[j] < S(0)) ? lam[j] : S(0);
+    const S c1 = g[0] * w1, c2 = g[1] * w2, c3 = g[2] * w3;
+    out[0] = c1 + c2 + c3;
+    out[1] = c1 * (u - a) + c2 * u + c3 * (u + a);
+    out[2] = c1 * (H - u * a) + c2 * (S(0.5) * u * u) + c3 * (H + u * a);
+    return isfinite(out[0]) && isfinite(out[1]) && isfinite(out[2]);
+  }
   __host__ __device__ static S pressure(const S* U, S gamma) {
     S m2 = S(0);
     for (int kk = 0; kk < DIM; ++kk) m2 += U[1 + kk] * U[1 + kk];
@@ -238,6 +290,9 @@ struct Cell<K_EULER, DIM, S> {
 template <int DIM, class S>
 struct Cell<K_MHD, DIM, S> {
   static constexpr int P = 9;
+  // Characteristic boundaries are not provided for MHD on the GPU (the
+  // solver rejects them at create); never called.
+  __host__ __device__ static bool char_correction(const S*, const S*, const Phys&, bool, S*) { return false; }
 
   __host__ __device__ static S pressure(const S* U, S gamma) {
     S m2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];

@@ -136,8 +136,13 @@ inline vklb_status validate(const vklb_system* sys, vklb_lattice lat, const vklb
     const double dy = (grid->hi[1] - grid->lo[1]) / double(grid->n[1]);
     if (!(fabs(dx - dy) <= 1e-12 * dx)) return bad(VKLB_ERR_ARG, "the D2Q5 lattice needs dx == dy");
   }
-  for (int a = 0; a < grid->dim; ++a)
-    if (bc[a] != VKLB_BC_PERIODIC && bc[a] != VKLB_BC_ZERO_GRADIENT) return bad(VKLB_ERR_ARG, "unknown bc");
+  for (int a = 0; a < grid->dim; ++a) {
+    if (bc[a] != VKLB_BC_PERIODIC && bc[a] != VKLB_BC_ZERO_GRADIENT && bc[a] != VKLB_BC_CHARACTERISTIC)
+      return bad(VKLB_ERR_ARG, "unknown bc");
+    if (bc[a] == VKLB_BC_CHARACTERISTIC && (grid->dim != 1 || sys->kind == VKLB_MHD_GLM))
+      return bad(VKLB_ERR_UNSUPPORTED, "characteristic boundaries: 1D shallow water, Euler and linear advection only");
+    if (bc[a] == VKLB_BC_CHARACTERISTIC && grid->n[0] < 2) return bad(VKLB_ERR_ARG, "characteristic boundaries need 2 cells");
+  }
   if (sys->kind == VKLB_SHALLOW_WATER && !(sys->g > 0.0)) return bad(VKLB_ERR_ARG, "g must be > 0");
   if ((sys->kind == VKLB_EULER || sys->kind == VKLB_MHD_GLM) && !(sys->gamma > 1.0))
     return bad(VKLB_ERR_ARG, "gamma must be > 1");
@@ -185,7 +190,7 @@ inline SolveDesc make_desc(char* base, const Layout& L, const vklb_system* sys, 
   d.nx = int(grid->n[0]);
   d.ny = grid->dim == 2 ? int(grid->n[1]) : 1;
   d.stride = L.stride;
-  d.bcx = bc[0] == VKLB_BC_PERIODIC ? 0 : 1;
+  d.bcx = bc[0] == VKLB_BC_PERIODIC ? 0 : (bc[0] == VKLB_BC_CHARACTERISTIC ? 2 : 1);
   d.bcy = (grid->dim == 2 ? bc[1] : bc[0]) == VKLB_BC_PERIODIC ? 0 : 1;
   d.band = band;
   d.halo = halo;

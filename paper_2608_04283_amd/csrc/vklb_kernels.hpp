@@ -335,6 +335,22 @@ struct Kern {
     for (int v = 0; v < P; ++v) out[v] = fq[v] - om * (fq[v] - T(plus ? fp[v] : fm[v]));
   }
 
+  // U of a stored cell: the rest slot in the delta bases, else the sum of
+  // the populations (in the order relax takes them).
+  __device__ static inline void moments_of(const T* __restrict__ src, long long cell, T (&U)[P]) {
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+      if (DELTA) {
+        U[v] = src[pidx(REST * P + v, cell)];
+      } else {
+        T s = T(0);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) s += src[pidx(q * P + v, cell)];
+        U[v] = s;
+      }
+    }
+  }
+
   __device__ static inline void collide(const T* __restrict__ src, long long cell, const Phys& ph,
                                         double ixi, double Lam, double ch, T (&fs)[Q][P], T (&U)[P]) {
     T f[Q][P];
@@ -418,10 +434,69 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
         Un[v] = ((T(0) + a) + fs[1][v]) + b;
       }
     }
-    K::new_state(sd, Un, x, n + 1, lam, cfm);
+    // characteristic boundaries: the boundary cells are replaced afterwards
+    if (!(sd.bcx == 2 && (x == 0 || x == N - 1))) K::new_state(sd, Un, x, n + 1, lam, cfm);
   }
   block_max2(lam, cfm, red_end);
   end_step(sd, S, tile, lam, cfm);
+}
+
+// Characteristic (non-reflecting) boundaries of Sec. 3.3, 1D, launched after
+// the step kernel of the same parity. From U^n of the boundary cell b and of
+// its interior neighbour (the step's source buffer): the characteristic
+// variables advance with the outgoing waves only (first-order one-sided
+// difference, linearized about b), U_b^{n+1} = U_b - P (Lambda dW)' / xi,
+// and b's populations in the new buffer become f^eq(U_b^{n+1}) with this
+// step's xi and Lambda. The step kernel left b out of its maxima; this kernel
+// folds U_b^{n+1}'s speeds into the partials of b's tile (0 or the last).
+template <int KIND, class T, int BASIS>
+__global__ void __launch_bounds__(64) k_char_bc1d(const SolveDesc sd) {
+  using K = Kern<KIND, 1, T, BASIS>;
+  using ST = typename K::ST;
+  constexpr int P = K::P, Q = 3;
+  __shared__ double red[4];
+  const Step S = begin_step(sd, red);  // every lane: the wave reductions need all 64
+  if (S.done || threadIdx.x != 0) return;
+  const int N = sd.nx;
+  if (N < 2) return;
+  const long long n = S.n;
+  const T* __restrict__ src = (const T*)((n & 1) ? sd.fb : sd.fa);
+  T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
+  const double ixi = 1.0 / S.xi;
+  double* pl = sd.part + (long long)(sd.par ^ 1) * 2 * sd.nblocks;
+  for (int side = 0; side < 2; ++side) {
+    const int b = side == 0 ? 0 : N - 1, nb = side == 0 ? 1 : N - 2;
+    T Ub[P], Unb[P];
+    K::moments_of(src, b, Ub);
+    K::moments_of(src, nb, Unb);
+    ST us[P], du[P], corr[P], unew[P];
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+      us[v] = ST(Ub[v]);
+      du[v] = side == 1 ? ST(Ub[v]) - ST(Unb[v]) : ST(Unb[v]) - ST(Ub[v]);
+    }
+    Cell<KIND, 1, ST>::char_correction(us, du, sd.ph, side == 1, corr);
+#pragma unroll
+    for (int v = 0; v < P; ++v) unew[v] = us[v] - corr[v] * ST(ixi);
+    ST fe[Q][P];
+    Equilibrium<KIND, 1, ST>::eval(unew, sd.ph, ST(ixi), ST(S.lam), ST(S.ch), fe);
+    T Ut[P];
+#pragma unroll
+    for (int v = 0; v < P; ++v) Ut[v] = T(unew[v]);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int v = 0; v < P; ++v) dst[K::pidx(q * P + v, b)] = (K::DELTA && q == K::REST) ? Ut[v] : T(fe[q][v]);
+    if (K::COMP) {
+#pragma unroll
+      for (int v = 0; v < P; ++v) dst[K::pidx(Q * P + v, b)] = T(0);
+    }
+    double lam = 0.0, cfm = 0.0;
+    K::new_state(sd, Ut, b, n + 1, lam, cfm);  // non-finite or non-physical: flagged here
+    const int tile = side == 0 ? 0 : sd.nblocks - 1;
+    pl[tile] = fmax(pl[tile], lam);
+    pl[sd.nblocks + tile] = fmax(pl[sd.nblocks + tile], cfm);
+  }
 }
 
 template <int KIND, class T, int BASIS, int B>

@@ -17,6 +17,7 @@ struct Launchers {
   launch_fn step = nullptr;
   launch_fn moments = nullptr;
   batched_fn batched = nullptr;  // serving: tiles of many solves in one launch
+  launch_fn char_bc = nullptr;   // 1D characteristic boundaries (SW, Euler, linear)
   int block = 256;  // threads per step workgroup
 };
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libvklb.so")
 OK, ERR_ARG, ERR_UNSUPPORTED, ERR_OOM, ERR_DEVICE, ERR_NONPHYSICAL, ERR_STATE = 0, -1, -2, -3, -4, -5, -6
 SYSTEMS = {"sw": 0, "shallow_water": 0, "euler": 1, "mhd": 2, "linear": 3}
 PRECISIONS = {"fp64": 0, "f64": 0, "fp32": 1, "f32": 1}
-BCS = {"periodic": 0, "zero_gradient": 1, "outflow": 1}
+BCS = {"periodic": 0, "zero_gradient": 1, "outflow": 1, "characteristic": 2}
 EQ_SETS = {"weighted": 0, "centered": 1, "discontinuous": 2}
 
 EXPORTED = ["vklb_workspace_bytes", "vklb_create", "vklb_set_end", "vklb_init", "vklb_init_device", "vklb_step", "vklb_moments",

@@ -90,6 +90,19 @@ def test_invalid_basis_rejected(vk, prec, basis):
     assert r == vk.ERR_ARG and "basis" in vk.lib().vklb_last_error(None).decode()
 
 
+def test_characteristic_boundary_scope(vk):
+    """Characteristic boundaries (Sec. 3.3) are provided for 1D shallow water,
+    Euler and linear advection; 2D grids and MHD are rejected as unsupported,
+    a one-cell grid as invalid."""
+    ch = ("characteristic", "characteristic")
+    r, msg = create(vk, I.quadrants(16, steps=1).with_(bc=ch))
+    assert r == vk.ERR_UNSUPPORTED and "characteristic" in msg
+    r, msg = create(vk, I.brio_wu(64).with_(bc=ch))
+    assert r == vk.ERR_UNSUPPORTED and "characteristic" in msg
+    r, msg = create(vk, I.sod(1).with_(bc=ch))
+    assert r == vk.ERR_ARG and "2 cells" in msg
+
+
 def test_tune_rejects_bad_step_count(vk):
     """Argument checks of vklb_tune come before any device call."""
     import numpy as np

@@ -12,6 +12,7 @@ import os
 import numpy as np
 import pytest
 
+from paper_2608_04283_amd import inputs as I
 from test_oracle_cell import rand_state, cfg, ch_for
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -29,6 +30,7 @@ def cc():
     L.vklb_cc_split.argtypes = [ctypes.c_int] * 4 + [dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
     L.vklb_cc_feq.argtypes = [ctypes.c_int] * 3 + [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
     L.vklb_cc_speeds.argtypes = [ctypes.c_int] * 3 + [dp, dp, dp, dp]
+    L.vklb_cc_char.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ctypes.c_int, dp]
     return L
 
 
@@ -161,3 +163,35 @@ def test_mhd_split_fp32_at_degenerate_states(oracle, cc, deg):
                 Fpo, _ = O.split(cf, d, U, ch, lam=Lam)
                 F, D = cc_split(cc, 4, "mhd", dim, d, U, pr, Lam, ch)
                 assert np.max(np.abs((0.5 * F + D) - Fpo)) < 1e-6 * (np.max(np.abs(F)) + 1.0)
+
+
+@pytest.mark.parametrize("system", ["sw", "euler", "linear"])
+@pytest.mark.parametrize("right", [True, False])
+def test_characteristic_correction_matches_oracle(oracle, cc, system, right):
+    """The closed-form characteristic boundary corrections (textbook left and
+    right eigenvectors) equal the oracle's eigenvector route: FP64 to 1e-12,
+    FP32 to 1e-6, relative to |A| |dU|."""
+    O = oracle
+    rng = np.random.default_rng(77)
+    cf = cfg(O, system, 1) if system != "linear" else O.make_config(system="linear", dim=1, n=(8, 1), adv=(0.7, 0.0))
+    pr = prm(gamma=1.4)
+    if system == "linear":
+        pr[3] = 0.7 if right else -0.7
+        cf = O.make_config(system="linear", dim=1, n=(8, 1), adv=(pr[3], 0.0))
+    for _ in range(20):
+        U = rand_state(system, 1, rng) if system != "linear" else np.array([rng.uniform(0.5, 2.0)])
+        # near-sonic states too: u close to +-c
+        if system == "euler" and _ % 4 == 0:
+            rho, p = U[0], 0.4 * (U[2] - 0.5 * U[1] ** 2 / U[0])
+            c = math.sqrt(1.4 * p / rho)
+            U = I.euler_state(np.array([rho]), c * (1 + 1e-3 * rng.normal()), p, 1.4)[:, 0]
+        dU = rng.normal(size=U.shape) * 0.1
+        ref = O.char_correction(cf, U, dU, 0.0, right=right)
+        scale = np.max(np.abs(O.jacobian(cf, 0, U, 0.0))) * np.max(np.abs(dU)) + 1e-300
+        for prec, tol in ((8, 1e-12), (4, 1e-6)):
+            out = np.zeros(len(U))
+            Uc = np.ascontiguousarray(U, dtype=np.float64)
+            dc = np.ascontiguousarray(dU, dtype=np.float64)
+            r = cc.vklb_cc_char(prec, KIND[system], _p(Uc), _p(dc), _p(pr), 1 if right else 0, _p(out))
+            assert r == len(U)
+            assert np.max(np.abs(out - ref)) < tol * scale, (system, prec, out, ref)

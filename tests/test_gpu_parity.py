@@ -10,6 +10,7 @@ import pytest
 
 from paper_2608_04283_amd import inputs as I
 from parity_util import rel_l1, run_oracle
+from test_oracle_boundaries import acoustic_pulse, linear1d
 
 pytestmark = pytest.mark.gpu
 
@@ -55,6 +56,14 @@ CASES = {
     "euler1d_sod_centered_preset_fp64": (lambda: I.sod(1500, eq_set="centered", nu=0.9), "fp64", {}),
     "euler1d_sod_discontinuous_preset_fp64": (lambda: I.sod(1500, eq_set="discontinuous", nu=0.5), "fp64", {}),
     "sw1d_dambreak_centered_preset_fp32": (lambda: I.dam_break(1000, eq_set="centered", nu=0.9), "fp32", {}),
+    "euler1d_sod_char_fp64": (lambda: I.sod(1500, bc=("characteristic", "characteristic")), "fp64", {}),
+    "euler1d_sod_char_fp32": (lambda: I.sod(1500, bc=("characteristic", "characteristic")), "fp32", {}),
+    "euler1d_pulse_char_fp64": (lambda: acoustic_pulse(400, 0.0, 1.0, 0.6), "fp64", {}),
+    "euler1d_pulse_char_fp32_delta": (lambda: acoustic_pulse(400, 0.0, 1.0, 0.6), "fp32", {"basis": 2}),
+    "sw1d_dambreak_char_fp64": (lambda: I.dam_break(1000, bc=("characteristic", "characteristic"), T=0.2), "fp64",
+                                {}),
+    "linear1d_char_fp64": (lambda: linear1d(300, 0.7, 2.0, 400, "characteristic"), "fp64", {}),
+    "linear1d_char_inflow_fp64": (lambda: linear1d(300, -0.7, 2.0, 400, "characteristic"), "fp64", {}),
     "mhd1d_briowu_fp64": (lambda: I.brio_wu(700), "fp64", {}),
     "mhd1d_briowu_fp32": (lambda: I.brio_wu(700), "fp32", {}),
     "sw1d_riemann_omega13_fp64": (lambda: I.random_riemann("sw", 1, 777, seed=5, omega=1.3, max_steps=300,
