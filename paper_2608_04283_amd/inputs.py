@@ -169,6 +169,37 @@ def smooth_wave(n=256, **kw) -> Problem:
     return P.with_(U0=euler_state(rho, np.ones_like(rho), np.ones_like(rho), P.gamma))
 
 
+def entropy_wave_2d(n=128, **kw) -> Problem:
+    """2D sinusoidal entropy wave (Sec. 5.2): rho = 1 + 0.1 sin(2 pi (x + y)),
+    u = v = 1, p = 1 on the periodic [0,1]^2; gamma = 1.4, nu = 0.3, omega = 2,
+    T = 1. The exact solution translates rho by t (u + v)."""
+    P = Problem(name=f"euler2d_entropy_wave_n{n}", system="euler", dim=2, n=(n, n), gamma=1.4, nu=0.3, omega=2.0,
+                T=1.0, bc=("periodic", "periodic"))
+    P = P.with_(**kw)
+    X, Y = grid2(n, n, P.lo, P.hi)
+    rho = 1.0 + 0.1 * np.sin(2 * np.pi * (X + Y))
+    one = np.ones_like(rho)
+    return P.with_(U0=euler_state(rho, one, one, P.gamma, v=one))
+
+
+def isentropic_vortex(n=128, eps=5.0, **kw) -> Problem:
+    """2D smooth vortex (Sec. 5.2) centred at the origin of the periodic
+    [-5,5]^2: T = 1 - (gamma-1) eps^2/(8 gamma pi^2) e^{1-r^2}, rho = T^{1/(gamma-1)},
+    (u, v) = (1, 1) + eps/(2 pi) e^{(1-r^2)/2} (-y, x), p = rho^gamma; gamma = 1.4,
+    nu = 0.3, omega = 2, T_end = 2. eps = 5: the paper leaves it unstated but
+    quotes Mach numbers 0.54 .. 1.97, which eps = 5 reproduces (0.547 .. 1.974)."""
+    P = Problem(name=f"euler2d_vortex_n{n}", system="euler", dim=2, n=(n, n), lo=(-5.0, -5.0), hi=(5.0, 5.0),
+                gamma=1.4, nu=0.3, omega=2.0, T=2.0, bc=("periodic", "periodic"))
+    P = P.with_(**kw)
+    X, Y = grid2(n, n, P.lo, P.hi)
+    g = P.gamma
+    r2 = X * X + Y * Y
+    Tt = 1.0 - (g - 1.0) * eps * eps / (8.0 * g * np.pi ** 2) * np.exp(1.0 - r2)
+    rho = Tt ** (1.0 / (g - 1.0))
+    e = eps / (2 * np.pi) * np.exp(0.5 * (1.0 - r2))
+    return P.with_(U0=euler_state(rho, 1.0 - e * Y, rho ** g, g, v=1.0 + e * X))
+
+
 def quadrants(n=2048, seed=0, steps=2000, **kw) -> Problem:
     """2D Euler four-quadrant Riemann data on [0,1]^2, gamma = 1.4.
 

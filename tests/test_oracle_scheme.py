@@ -134,7 +134,7 @@ def lb_amplification(theta, omega, e, m):
     return S @ ((1 - omega) * np.eye(Qn) + omega * np.outer(e, np.ones(Qn)))
 
 
-@pytest.mark.parametrize("omega", [0.6, 1.0, 1.5, 1.9])
+@pytest.mark.parametrize("omega", [0.6, 1.0, 1.5, 1.9, 2.0])
 @pytest.mark.parametrize("a", [0.7, -0.4])
 def test_linear_advection_fourier_1d(oracle, omega, a):
     """For F = a U the scheme is linear; each Fourier mode evolves by the exact
@@ -158,7 +158,7 @@ def test_linear_advection_fourier_1d(oracle, omega, a):
     assert np.allclose(r["U"][0], ref, rtol=1e-11, atol=1e-11)
 
 
-@pytest.mark.parametrize("omega", [1.0, 1.7])
+@pytest.mark.parametrize("omega", [1.0, 1.7, 2.0])
 def test_linear_advection_fourier_2d(oracle, omega):
     O = oracle
     n, steps, xi, c, k = 16, 12, 2.0, 0.05, 2.0

@@ -1,0 +1,38 @@
+"""The smooth 2D Euler problems of Sec. 5.2 on the oracle (no GPU), against
+their exact solutions: the isentropic vortex converges at second order at
+omega = 2 with the weighted-upwind and the centered sets (the weighted one
+more accurate), the entropy wave too with the centered set, and the weighted
+set is much more accurate there on a coarse grid."""
+import math
+
+import pytest
+
+from paper_2608_04283_amd import inputs as I
+import exact_smooth as E
+from parity_util import run_oracle
+from smooth_util import fixed_xi
+
+
+def err(O, P, prob):
+    P, t = fixed_xi(P)
+    r = run_oracle(O, P)
+    assert r["status"] == 0
+    ref = E.entropy_wave_density(P, t) if prob == "wave" else E.vortex_state(P, t)[0]
+    return E.l2(r["U"][0], ref)
+
+
+@pytest.mark.parametrize("eq_set", ["weighted", "centered"])
+def test_vortex_second_order_at_omega_two(oracle, eq_set):
+    e = [err(oracle, I.isentropic_vortex(n, eq_set=eq_set, T=0.5), "vortex") for n in (32, 64)]
+    order = math.log2(e[0] / e[1])
+    print(f"[vortex {eq_set}] {e} order {order:.2f}")
+    assert order > 1.8
+
+
+def test_weighted_more_accurate_than_centered(oracle):
+    wv = err(oracle, I.isentropic_vortex(48, T=0.5), "vortex")
+    cv = err(oracle, I.isentropic_vortex(48, T=0.5, eq_set="centered"), "vortex")
+    ww = err(oracle, I.entropy_wave_2d(64), "wave")
+    cw = err(oracle, I.entropy_wave_2d(64, eq_set="centered"), "wave")
+    print(f"[accuracy] vortex {wv:.2e} vs {cv:.2e}; wave {ww:.2e} vs {cw:.2e}")
+    assert wv < cv and ww < 0.2 * cw
