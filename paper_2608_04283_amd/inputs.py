@@ -159,6 +159,54 @@ def sod(n=65536, **kw) -> Problem:
     return P.with_(U0=euler_state(rho, np.zeros_like(rho), p, P.gamma))
 
 
+def sw_riemann(which="standard", n=1024, **kw) -> Problem:
+    """The shallow water Riemann problems of Sec. 5.1 (g = 1, x0 = 0):
+
+    * standard dam break: h = 3 | 1, hu = 0 | 0 on [-5, 5], t = 2;
+    * hydraulic flow: h = 10 | 1, hu = 0 | 0 on [-20, 20], t = 4 (the Froude
+      number crosses one inside the rarefaction);
+    * compression flow: h = 1 | 1, hu = 1 | -1 on [-2, 2], t = 0.5 (one
+      eigenvalue starts at zero everywhere).
+    The paper runs them at CFL 0.9, 0.8 and 0.9 respectively."""
+    table = {
+        "standard": ((-5.0, 5.0), 2.0, (3.0, 1.0), (0.0, 0.0), 0.9),
+        "hydraulic": ((-20.0, 20.0), 4.0, (10.0, 1.0), (0.0, 0.0), 0.8),
+        "compression": ((-2.0, 2.0), 0.5, (1.0, 1.0), (1.0, -1.0), 0.9),
+    }
+    (a, b), T, (hl, hr), (ql, qr), nu = table[which]
+    P = Problem(name=f"sw1d_{which}_n{n}", system="sw", dim=1, n=(n,), lo=(a, 0.0), hi=(b, 1.0), g=1.0, nu=nu,
+                T=T)
+    P = P.with_(**kw)
+    x = cell_centres(n, P.lo[0], P.hi[0])
+    left = x < 0.0
+    h = np.where(left, hl, hr)
+    hu = np.where(left, ql, qr)
+    return P.with_(U0=sw_state(h, hu / h))
+
+
+def euler_riemann(which="sod", n=1024, **kw) -> Problem:
+    """The Euler Riemann problems of Sec. 5.2 (CFL 0.9):
+
+    * Sod: (rho, u, p) = (1, 0, 1) | (0.125, 0, 0.1) on [-0.5, 0.5], x0 = 0, t = 0.2, gamma = 1.4;
+    * Leblanc: (1, 0, 6.667e-2) | (1e-3, 0, 6.667e-9) on [0, 9], x0 = 3, t = 6, gamma = 5/3
+      (eight decades of energy across the jump);
+    * sonic point: (1, 0.75, 1) | (0.125, 0.75, 0.1) on [-1, 1], x0 = -0.4, t = 0.5, gamma = 1.4
+      (the left rarefaction is transonic)."""
+    table = {
+        "sod": ((-0.5, 0.5), 0.2, 0.0, (1.0, 0.125), (0.0, 0.0), (1.0, 0.1), 1.4),
+        "leblanc": ((0.0, 9.0), 6.0, 3.0, (1.0, 1e-3), (0.0, 0.0), (6.667e-2, 6.667e-9), 5.0 / 3.0),
+        "sonic": ((-1.0, 1.0), 0.5, -0.4, (1.0, 0.125), (0.75, 0.75), (1.0, 0.1), 1.4),
+    }
+    (a, b), T, x0, (rl, rr), (ul, ur), (pl, pr), gamma = table[which]
+    P = Problem(name=f"euler1d_{which}_n{n}", system="euler", dim=1, n=(n,), lo=(a, 0.0), hi=(b, 1.0),
+                gamma=gamma, nu=0.9, T=T)
+    P = P.with_(**kw)
+    x = cell_centres(n, P.lo[0], P.hi[0])
+    left = x < x0
+    return P.with_(U0=euler_state(np.where(left, rl, rr), np.where(left, ul, ur), np.where(left, pl, pr),
+                                  P.gamma))
+
+
 def smooth_wave(n=256, **kw) -> Problem:
     """Periodic Euler density wave rho = 1 + 0.2 sin(2 pi x), u = 1, p = 1; exact solution rho(x - t)."""
     P = Problem(name=f"euler1d_wave_n{n}", system="euler", dim=1, n=(n,), gamma=1.4, nu=0.3, T=1.0,

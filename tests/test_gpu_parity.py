@@ -87,6 +87,27 @@ CASES = {
     "mhd2d_riemann_fp32": (lambda: I.random_riemann("mhd", 2, 100, seed=9, max_steps=60), "fp32", {}),
     "mhd2d_ot_fp32_compensated": (lambda: I.orszag_tang(96, steps=60), "fp32", {"basis": 3}),
     "linear2d_omega17_fp64": (lambda: linear2d(70, 40, 1.7), "fp64", {}),
+    # the shallow water and Euler Riemann tables of Sec. 5.1 / 5.2 and the omega sweep of Sec. 6
+    "sw1d_hydraulic_fp64": (lambda: I.sw_riemann("hydraulic", 1500), "fp64", {}),
+    "sw1d_hydraulic_fp32": (lambda: I.sw_riemann("hydraulic", 1500), "fp32", {}),
+    "sw1d_hydraulic_centered_fp32": (lambda: I.sw_riemann("hydraulic", 1500, eq_set="centered"), "fp32", {}),
+    "sw1d_compression_fp64": (lambda: I.sw_riemann("compression", 1300), "fp64", {}),
+    # (compression flow under the discontinuous split amplifies round-off to O(1) within ten steps, so its
+    # answer is not unique and it has no parity case; the hydraulic flow's oscillations are deterministic)
+    "sw1d_hydraulic_discontinuous_fp64": (lambda: I.sw_riemann("hydraulic", 1300, eq_set="discontinuous"),
+                                          "fp64", {}),
+    "sw1d_standard_fp32_delta": (lambda: I.sw_riemann("standard", 1100), "fp32", {"basis": 2}),
+    "euler1d_leblanc_fp64": (lambda: I.euler_riemann("leblanc", 2000), "fp64", {}),
+    "euler1d_leblanc_fp32": (lambda: I.euler_riemann("leblanc", 2000), "fp32", {}),
+    "euler1d_leblanc_discontinuous_fp64": (lambda: I.euler_riemann("leblanc", 2000, eq_set="discontinuous"),
+                                           "fp64", {}),
+    "euler1d_sonic_fp64": (lambda: I.euler_riemann("sonic", 1700), "fp64", {}),
+    "euler1d_sonic_fp32": (lambda: I.euler_riemann("sonic", 1700), "fp32", {}),
+    "euler1d_sonic_discontinuous_fp32": (lambda: I.euler_riemann("sonic", 1700, eq_set="discontinuous"), "fp32",
+                                         {}),
+    "euler1d_sod_omega14_fp64": (lambda: I.euler_riemann("sod", 1000, omega=1.4), "fp64", {}),
+    "mhd1d_briowu_omega13_fp64": (lambda: I.brio_wu(700, omega=1.3), "fp64", {}),
+    "mhd1d_briowu_centered_omega16_fp32": (lambda: I.brio_wu(700, eq_set="centered", omega=1.6), "fp32", {}),
 }
 
 
