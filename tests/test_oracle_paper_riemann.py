@@ -9,7 +9,8 @@ textbook theory):
   eigenvalue changes sign (total variation blow-up in the shallow water
   cases, a stationary jump at the sonic point of the Euler rarefactions);
 * the relaxation sweep of Sec. 6 (omega > 1 on Sod and Brio-Wu): the
-  thresholds at which each set loses positivity.
+  thresholds at which each set loses positivity;
+* the CFL limit of the discontinuous set on Brio-Wu (Sec. 5.3).
 """
 import numpy as np
 import pytest
@@ -216,3 +217,21 @@ def test_omega_sweep_sod_oscillations_grow_until_breakdown(oracle):
         assert rise[eq_set, 1.4] > 10.0 * rise[eq_set, 1.0], rise
     r = run_oracle(oracle, I.euler_riemann("sod", n, eq_set="weighted", omega=1.6))
     assert r["status"] == 1
+
+
+def test_brio_wu_discontinuous_set_cfl_limit(oracle):
+    """Sec. 5.3: on Brio-Wu the discontinuous set needs nu <= 0.45 (the
+    pressure turns negative above it) while the centered and weighted sets run
+    at 0.9. That limit holds when the streaming speed follows the physical
+    waves only. In 1D, B_x and psi stay exactly uniform, so the cleaning speed
+    enters only through Lambda, and c_h = max c_f (ch_factor = 1) gives exactly
+    that reading. With the cleaning speed 6 max c_f inside Lambda (the default,
+    which reproduces the omega thresholds of Sec. 6 exactly) the physical waves
+    run at a sixth of nu and the discontinuous set is stable at 0.9 as well."""
+    for n in (400, 1600):
+        for nu, ok in ((0.45, True), (0.5, False), (0.9, False)):
+            r = run_oracle(oracle, I.brio_wu(n, eq_set="discontinuous", nu=nu, ch_factor=1.0))
+            assert (r["status"] == 0) == ok, (n, nu)
+        for eq_set in ("weighted", "centered"):
+            assert run_oracle(oracle, I.brio_wu(n, eq_set=eq_set, nu=0.9, ch_factor=1.0))["status"] == 0
+    assert run_oracle(oracle, I.brio_wu(400, eq_set="discontinuous", nu=0.9))["status"] == 0

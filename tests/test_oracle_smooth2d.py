@@ -36,3 +36,20 @@ def test_weighted_more_accurate_than_centered(oracle):
     cw = err(oracle, I.entropy_wave_2d(64, eq_set="centered"), "wave")
     print(f"[accuracy] vortex {wv:.2e} vs {cv:.2e}; wave {ww:.2e} vs {cw:.2e}")
     assert wv < cv and ww < 0.2 * cw
+
+
+@pytest.mark.parametrize("prob", ["wave", "vortex"])
+def test_discontinuous_set_unstable_on_smooth_problems(oracle, prob):
+    """Sec. 5.2: at omega = 2 the discontinuous split fails on both smooth
+    problems at every CFL number the paper tried (0.05 to 0.3): here the run
+    turns non-physical before the end time on the 64^2 lattice, while the
+    weighted set on the same lattice and speed reaches it."""
+    for nu in (0.05, 0.1, 0.2, 0.3):
+        for eq_set in ("discontinuous", "weighted"):
+            make = I.entropy_wave_2d if prob == "wave" else I.isentropic_vortex
+            P, _ = fixed_xi(make(64, eq_set=eq_set, nu=nu, omega=2.0))
+            r = run_oracle(oracle, P)
+            if eq_set == "discontinuous":
+                assert r["status"] == 1 and r["steps"] < P.max_steps, (nu, r["steps"])
+            else:
+                assert r["status"] == 0 and r["steps"] == P.max_steps, nu
