@@ -83,13 +83,14 @@ typedef struct {
  *  periodic (Sec. 3.3);
  *  zero gradient (the ghost beyond a boundary carries the post-collision
  *    populations of the boundary cell);
- *  characteristic, non-reflecting (Sec. 3.3; 1D shallow water, Euler and
- *    linear advection; VKLB_ERR_UNSUPPORTED otherwise, and in the serving
- *    pool): at a boundary cell the characteristic variables W = P^{-1} U
- *    advance with the outgoing waves only, dW/dx taken as the first-order
- *    one-sided difference towards the interior, U_b^{n+1} = U_b - P
- *    (Lambda dW)' / xi, and the cell's populations become f^eq(U_b^{n+1})
- *    with the step's xi. Both ends of the axis use it (bc[0] in 1D). */
+ *  characteristic, non-reflecting (Sec. 3.3; 1D only, every system;
+ *    VKLB_ERR_UNSUPPORTED in 2D and in the serving pool): at a boundary cell
+ *    the characteristic variables W = P^{-1} U advance with the outgoing
+ *    waves only, dW/dx taken as the first-order one-sided difference towards
+ *    the interior, U_b^{n+1} = U_b - P (Lambda dW)' / xi, and the cell's
+ *    populations become f^eq(U_b^{n+1}) with the step's xi. For MHD the nine
+ *    waves include the cleaning pair +-c_h at the step's c_h. Both ends of
+ *    the axis use it (bc[0] in 1D). */
 typedef enum { VKLB_BC_PERIODIC = 0, VKLB_BC_ZERO_GRADIENT = 1, VKLB_BC_CHARACTERISTIC = 2 } vklb_bc;
 
 /* Equilibrium distribution set.

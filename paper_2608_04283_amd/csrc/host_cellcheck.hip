@@ -84,20 +84,21 @@ int speeds_any(int kind, int dim, const double* U, const double* prm, double* la
 }
 
 template <int KIND, class S>
-int run_char(const double* U, const double* dU, const double* prm, int right, double* out) {
+int run_char(const double* U, const double* dU, const double* prm, double ch, int right, double* out) {
   using C = Cell<KIND, 1, S>;
   S u[C::P], du[C::P], o[C::P];
   for (int i = 0; i < C::P; ++i) { u[i] = S(U[i]); du[i] = S(dU[i]); }
-  if (!C::char_correction(u, du, make_phys<S>(prm), right != 0, o)) return -1;
+  if (!C::char_correction(u, du, make_phys<S>(prm), S(ch), right != 0, o)) return -1;
   for (int i = 0; i < C::P; ++i) out[i] = double(o[i]);
   return C::P;
 }
 template <class S>
-int char_any(int kind, const double* U, const double* dU, const double* prm, int right, double* out) {
+int char_any(int kind, const double* U, const double* dU, const double* prm, double ch, int right, double* out) {
   switch (kind) {
-    case K_SW: return run_char<K_SW, S>(U, dU, prm, right, out);
-    case K_EULER: return run_char<K_EULER, S>(U, dU, prm, right, out);
-    case K_LINEAR: return run_char<K_LINEAR, S>(U, dU, prm, right, out);
+    case K_SW: return run_char<K_SW, S>(U, dU, prm, ch, right, out);
+    case K_EULER: return run_char<K_EULER, S>(U, dU, prm, ch, right, out);
+    case K_MHD: return run_char<K_MHD, S>(U, dU, prm, ch, right, out);
+    case K_LINEAR: return run_char<K_LINEAR, S>(U, dU, prm, ch, right, out);
   }
   return -1;
 }
@@ -106,9 +107,11 @@ int char_any(int kind, const double* U, const double* dU, const double* prm, int
 
 extern "C" {
 // Characteristic boundary correction P (Lambda dW)' of a 1D system (SW,
-// Euler, linear). Returns p, or -1.
-int vklb_cc_char(int prec, int kind, const double* U, const double* dU, const double* prm, int right, double* out) {
-  return prec == 4 ? char_any<float>(kind, U, dU, prm, right, out) : char_any<double>(kind, U, dU, prm, right, out);
+// Euler, MHD with cleaning speed ch, linear). Returns p, or -1.
+int vklb_cc_char(int prec, int kind, const double* U, const double* dU, const double* prm, double ch, int right,
+                 double* out) {
+  return prec == 4 ? char_any<float>(kind, U, dU, prm, ch, right, out)
+                   : char_any<double>(kind, U, dU, prm, ch, right, out);
 }
 // prec: 8 -> double arithmetic, 4 -> float arithmetic. Returns p, or -1.
 int vklb_cc_split(int prec, int kind, int dim, int d, const double* U, const double* prm, double Lam, double ch,

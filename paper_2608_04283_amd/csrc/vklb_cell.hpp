@@ -127,7 +127,7 @@ struct Cell<K_LINEAR, DIM, S> {
   static constexpr int P = 1;
   // Characteristic boundary of Sec. 3.3 (1D): out = g(a) dU with g(a) = a for
   // an outgoing wave (a > 0 at the right boundary, a < 0 at the left), else 0.
-  __host__ __device__ static bool char_correction(const S* Ub, const S* dU, const Phys& ph, bool right, S* out) {
+  __host__ __device__ static bool char_correction(const S* Ub, const S* dU, const Phys& ph, S, bool right, S* out) {
     (void)Ub;
     const S a = S(ph.adv[0]);
     out[0] = (right ? a > S(0) : a < S(0)) ? a * dU[0] : S(0);
@@ -157,7 +157,7 @@ struct Cell<K_SW, DIM, S> {
   // Characteristic boundary of Sec. 3.3 (1D): out = sum_j g(lambda_j) (l_j . dU) r_j
   // over u -+ c, with r = (1, u -+ c), l = (+-(u +- c), -+1) / (2c) and g the
   // speed for outgoing waves, 0 for incoming ones.
-  __host__ __device__ static bool char_correction(const S* Ub, const S* dU, const Phys& ph, bool right, S* out) {
+  __host__ __device__ static bool char_correction(const S* Ub, const S* dU, const Phys& ph, S, bool right, S* out) {
     const S h = Ub[0];
     const S u = qdiv(Ub[1], h);
     const S c = qsqrt(S(ph.g) * h);
@@ -213,7 +213,7 @@ struct Cell<K_EULER, DIM, S> {
   // (1, u, u^2/2) and left eigenvectors (b1 = (gamma-1)/a^2, b2 = b1 u^2/2)
   // l_1,3 = (b2 +- u/a, -(b1 u +- 1/a), b1)/2, l_2 = (1 - b2, b1 u, -b1);
   // g is the speed for outgoing waves, 0 for incoming ones.
-  __host__ __device__ static bool char_correction(const S* Ub, const S* dU, const Phys& ph, bool right, S* out) {
+  __host__ __device__ static bool char_correction(const S* Ub, const S* dU, const Phys& ph, S, bool right, S* out) {
     const S gamma = S(ph.gamma);
     const S rho = Ub[0];
     const S u = qdiv(Ub[1], rho);
@@ -290,9 +290,94 @@ struct Cell<K_EULER, DIM, S> {
 template <int DIM, class S>
 struct Cell<K_MHD, DIM, S> {
   static constexpr int P = 9;
-  // Characteristic boundaries are not provided for MHD on the GPU (the
-  // solver rejects them at create); never called.
-  __host__ __device__ static bool char_correction(const S*, const S*, const Phys&, bool, S*) { return false; }
+  // Characteristic boundary of Sec. 3.3 (1D, normal x): out = g(A) dU with
+  // g(lambda) = lambda for waves leaving through the boundary and 0 for the
+  // others, over the nine waves of the GLM system: the seven MHD waves through
+  // the primitive eigenvectors of the split below, the cleaning pair +-c_h on
+  // (B_n, psi), and the pair's coupling into the seven-wave block through the
+  // B_n column of the Jacobian, by divided differences of g (the Jacobian is
+  // block triangular). Computed in FP64 in both precisions: it runs on two
+  // cells per step.
+  __host__ __device__ static bool char_correction(const S* Ub, const S* dU, const Phys& ph, S ch, bool right,
+                                                  S* out) {
+    double U[9], dv[9], o[9];
+    for (int i = 0; i < 9; ++i) {
+      U[i] = double(Ub[i]);
+      dv[i] = double(dU[i]);
+    }
+    if (!char64(U, dv, ph, double(ch), right, o)) return false;
+    bool ok = true;
+    for (int i = 0; i < 9; ++i) {
+      out[i] = S(o[i]);
+      ok = ok && isfinite(out[i]);
+    }
+    return ok;
+  }
+  __host__ __device__ static bool char64(const double* Ug, const double* dv, const Phys& ph, double ch, bool right,
+                                         double* out) {
+    using C = Cell<K_MHD, DIM, double>;
+    if (!(ch > 0.0)) return false;
+    const double gamma = ph.gamma, gm1 = gamma - 1.0;
+    const double rho = Ug[0], irho = 1.0 / rho;
+    const double u = Ug[1] * irho, v = Ug[2] * irho, w = Ug[3] * irho;
+    const double Bn = Ug[5], By = Ug[6], Bz = Ug[7];
+    const double uu = u * u + v * v + w * w;
+    const double p = gm1 * (Ug[4] - 0.5 * rho * uu - 0.5 * (Bn * Bn + By * By + Bz * Bz));
+    double eg[9];
+    C::template eigenstructure<double>(rho, p, Bn, By, Bz, gamma, eg);
+    typename C::Waves W;
+    W.rho = rho;
+    W.sr = sqrt(rho);
+    W.a2 = eg[0];
+    W.a = eg[1];
+    W.cf = eg[2];
+    W.cs = eg[3];
+    const double ca = eg[4];
+    W.af = eg[5];
+    W.as = eg[6];
+    W.by = eg[7];
+    W.bz = eg[8];
+    W.sgn = Bn >= 0.0 ? 1.0 : -1.0;
+    const double lam[7] = {u - W.cf, u - ca, u - W.cs, u, u + W.cs, u + ca, u + W.cf};
+    auto out_ = [right](double l) { return right ? l > 0.0 : l < 0.0; };
+    auto g = [&](double l) { return out_(l) ? l : 0.0; };
+    auto dd = [&](double a, double b) { return a != b ? (g(a) - g(b)) / (a - b) : (out_(a) ? 1.0 : 0.0); };
+    // primitive images (B_n held fixed) of the seven-wave part of dU and of
+    // the B_n column of the Jacobian
+    double x[7], xC[7];
+    x[0] = dv[0];
+    x[1] = (dv[1] - u * dv[0]) * irho;
+    x[2] = (dv[2] - v * dv[0]) * irho;
+    x[3] = (dv[3] - w * dv[0]) * irho;
+    x[4] = gm1 * (dv[4] + 0.5 * uu * dv[0] - (u * dv[1] + v * dv[2] + w * dv[3]) - By * dv[6] - Bz * dv[7]);
+    x[5] = dv[6];
+    x[6] = dv[7];
+    xC[0] = 0.0;
+    xC[1] = -gamma * Bn * irho;
+    xC[2] = -By * irho;
+    xC[3] = -Bz * irho;
+    xC[4] = gm1 * (v * By + w * Bz);
+    xC[5] = -v;
+    xC[6] = -w;
+    double c[7], cC[7], cD[7];
+    C::project(W, x, c);
+    C::project(W, xC, cC);
+    // cleaning pair: eigenvalues +-c_h, eigenvectors (1, +-c_h) on (B_n, psi)
+    const double qp = 0.5 * (dv[5] + dv[8] / ch), qm = 0.5 * (dv[5] - dv[8] / ch);
+    for (int j = 0; j < 7; ++j) cD[j] = g(lam[j]) * c[j] + (dd(lam[j], ch) * qp + dd(lam[j], -ch) * qm) * cC[j];
+    double y[7];
+    C::combine(W, cD, y);
+    out[0] = y[0];
+    out[1] = u * y[0] + rho * y[1];
+    out[2] = v * y[0] + rho * y[2];
+    out[3] = w * y[0] + rho * y[3];
+    out[4] = y[4] / gm1 + 0.5 * uu * y[0] + rho * (u * y[1] + v * y[2] + w * y[3]) + By * y[5] + Bz * y[6];
+    out[6] = y[5];
+    out[7] = y[6];
+    out[5] = g(ch) * qp + g(-ch) * qm;
+    out[8] = ch * (g(ch) * qp - g(-ch) * qm);
+    return true;
+  }
 
   __host__ __device__ static S pressure(const S* U, S gamma) {
     S m2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];

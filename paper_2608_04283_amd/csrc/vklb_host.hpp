@@ -139,8 +139,8 @@ inline vklb_status validate(const vklb_system* sys, vklb_lattice lat, const vklb
   for (int a = 0; a < grid->dim; ++a) {
     if (bc[a] != VKLB_BC_PERIODIC && bc[a] != VKLB_BC_ZERO_GRADIENT && bc[a] != VKLB_BC_CHARACTERISTIC)
       return bad(VKLB_ERR_ARG, "unknown bc");
-    if (bc[a] == VKLB_BC_CHARACTERISTIC && (grid->dim != 1 || sys->kind == VKLB_MHD_GLM))
-      return bad(VKLB_ERR_UNSUPPORTED, "characteristic boundaries: 1D shallow water, Euler and linear advection only");
+    if (bc[a] == VKLB_BC_CHARACTERISTIC && grid->dim != 1)
+      return bad(VKLB_ERR_UNSUPPORTED, "characteristic boundaries: 1D only");
     if (bc[a] == VKLB_BC_CHARACTERISTIC && grid->n[0] < 2) return bad(VKLB_ERR_ARG, "characteristic boundaries need 2 cells");
   }
   if (sys->kind == VKLB_SHALLOW_WATER && !(sys->g > 0.0)) return bad(VKLB_ERR_ARG, "g must be > 0");

@@ -91,14 +91,15 @@ def test_invalid_basis_rejected(vk, prec, basis):
 
 
 def test_characteristic_boundary_scope(vk):
-    """Characteristic boundaries (Sec. 3.3) are provided for 1D shallow water,
-    Euler and linear advection; 2D grids and MHD are rejected as unsupported,
-    a one-cell grid as invalid."""
+    """Characteristic boundaries (Sec. 3.3) are provided in 1D for every
+    system; 2D grids are rejected as unsupported, a one-cell grid as invalid
+    (the 1D MHD request passes validation and stops only at the missing
+    device buffer)."""
     ch = ("characteristic", "characteristic")
     r, msg = create(vk, I.quadrants(16, steps=1).with_(bc=ch))
     assert r == vk.ERR_UNSUPPORTED and "characteristic" in msg
     r, msg = create(vk, I.brio_wu(64).with_(bc=ch))
-    assert r == vk.ERR_UNSUPPORTED and "characteristic" in msg
+    assert r != vk.ERR_UNSUPPORTED and "characteristic" not in msg
     r, msg = create(vk, I.sod(1).with_(bc=ch))
     assert r == vk.ERR_ARG and "2 cells" in msg
 

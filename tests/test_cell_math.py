@@ -30,7 +30,7 @@ def cc():
     L.vklb_cc_split.argtypes = [ctypes.c_int] * 4 + [dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
     L.vklb_cc_feq.argtypes = [ctypes.c_int] * 3 + [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
     L.vklb_cc_speeds.argtypes = [ctypes.c_int] * 3 + [dp, dp, dp, dp]
-    L.vklb_cc_char.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ctypes.c_int, dp]
+    L.vklb_cc_char.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ctypes.c_double, ctypes.c_int, dp]
     return L
 
 
@@ -192,6 +192,34 @@ def test_characteristic_correction_matches_oracle(oracle, cc, system, right):
             out = np.zeros(len(U))
             Uc = np.ascontiguousarray(U, dtype=np.float64)
             dc = np.ascontiguousarray(dU, dtype=np.float64)
-            r = cc.vklb_cc_char(prec, KIND[system], _p(Uc), _p(dc), _p(pr), 1 if right else 0, _p(out))
+            r = cc.vklb_cc_char(prec, KIND[system], _p(Uc), _p(dc), _p(pr), 0.0, 1 if right else 0, _p(out))
             assert r == len(U)
             assert np.max(np.abs(out - ref)) < tol * scale, (system, prec, out, ref)
+
+
+@pytest.mark.parametrize("right", [True, False])
+def test_mhd_characteristic_correction_matches_oracle(oracle, cc, right):
+    """The MHD characteristic correction (primitive Roe-Balsara eigenvectors,
+    the cleaning pair and their coupling by divided differences of g) equals
+    the oracle's route (eigenvectors as null vectors of the Jacobian, LU) at
+    random states, at states where speeds coincide exactly (transverse or
+    normal field zero) and near the triple point; it is computed in FP64 in
+    both precisions, so FP32 differs only by the rounding of its inputs."""
+    O = oracle
+    rng = np.random.default_rng(78)
+    cf = cfg(O, "mhd", 1)
+    pr = prm(gamma=2.0)
+    for i in range(40):
+        deg = (None, "bt0", "bx0", "triple_near", None)[i % 5]
+        U = rand_state("mhd", 1, rng, degenerate=deg)
+        ch = ch_for(O, cf, U)
+        dU = rng.normal(size=U.shape) * 0.1
+        ref = O.char_correction(cf, U, dU, ch, right=right)
+        scale = np.max(np.abs(O.jacobian(cf, 0, U, ch))) * np.max(np.abs(dU))
+        for prec, tol in ((8, 1e-10 if deg == "triple_near" else 1e-12), (4, 1e-6)):
+            out = np.zeros(len(U))
+            Uc = np.ascontiguousarray(U, dtype=np.float64)
+            dc = np.ascontiguousarray(dU, dtype=np.float64)
+            r = cc.vklb_cc_char(prec, KIND["mhd"], _p(Uc), _p(dc), _p(pr), ch, 1 if right else 0, _p(out))
+            assert r == len(U)
+            assert np.max(np.abs(out - ref)) < tol * scale, (deg, prec, np.max(np.abs(out - ref)) / scale)

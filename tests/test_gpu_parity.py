@@ -108,10 +108,11 @@ CASES = {
     "euler1d_sod_omega14_fp64": (lambda: I.euler_riemann("sod", 1000, omega=1.4), "fp64", {}),
     "mhd1d_briowu_omega13_fp64": (lambda: I.brio_wu(700, omega=1.3), "fp64", {}),
     "mhd1d_briowu_centered_omega16_fp32": (lambda: I.brio_wu(700, eq_set="centered", omega=1.6), "fp32", {}),
-    # Lambda from the physical waves (c_h = max c_f; B_x and psi stay uniform in 1D)
-    "mhd1d_briowu_discontinuous_ch1_nu045_fp64": (lambda: I.brio_wu(700, eq_set="discontinuous", nu=0.45,
-                                                                     ch_factor=1.0), "fp64", {}),
-    "mhd1d_briowu_ch1_fp32": (lambda: I.brio_wu(700, ch_factor=1.0), "fp32", {}),
+    # (Brio-Wu with Lambda from the physical waves, ch_factor = 1, has no case: at a physical CFL near 0.9 it
+    # amplifies a 1e-16 perturbation of the data to 1e-5..1e-4, so its answer is not unique in floating point)
+    # characteristic boundaries for MHD, run until the fast waves have left through both ends
+    "mhd1d_briowu_char_fp64": (lambda: I.brio_wu(700, T=0.3, bc=("characteristic", "characteristic")), "fp64", {}),
+    "mhd1d_briowu_char_fp32": (lambda: I.brio_wu(700, T=0.3, bc=("characteristic", "characteristic")), "fp32", {}),
 }
 
 
