@@ -149,40 +149,58 @@ __device__ inline double wave_max(double v) {
   return __longlong_as_double((long long)(((unsigned long long)hm << 32) | lm));
 }
 
-// Block max of (a, b) into lane 0 of wave 0; `red` needs 2 * (blockDim/64) doubles.
+// Block max of (a, b) into lane 0 of wave 0; `red` needs 2 * (blockDim/64)
+// doubles. TWO = false (systems without a cleaning speed, whose fast-speed
+// maxima are identically 0) reduces a alone and leaves b as it is.
+template <bool TWO = true>
 __device__ inline void block_max2(double& a, double& b, double* red) {
   a = wave_max(a);
-  b = wave_max(b);
+  if (TWO) b = wave_max(b);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if (lane == 0) { red[wid] = a; red[nw + wid] = b; }
+  if (lane == 0) {
+    red[wid] = a;
+    if (TWO) red[nw + wid] = b;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 1; w < nw; ++w) { a = fmax(a, red[w]); b = fmax(b, red[nw + w]); }
+    for (int w = 1; w < nw; ++w) {
+      a = fmax(a, red[w]);
+      if (TWO) b = fmax(b, red[nw + w]);
+    }
   }
 }
 
 // Block max of (a, b) broadcast to every lane; `red` needs 2 * (blockDim/64)
 // doubles and is not written again by this workgroup (no trailing barrier).
+template <bool TWO = true>
 __device__ inline void block_max2_all(double& a, double& b, double* red) {
   a = wave_max(a);
-  b = wave_max(b);
+  if (TWO) b = wave_max(b);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if (lane == 0) { red[wid] = a; red[nw + wid] = b; }
+  if (lane == 0) {
+    red[wid] = a;
+    if (TWO) red[nw + wid] = b;
+  }
   __syncthreads();
-  for (int w = 0; w < nw; ++w) { a = fmax(a, red[w]); b = fmax(b, red[nw + w]); }
+  for (int w = 0; w < nw; ++w) {
+    a = fmax(a, red[w]);
+    if (TWO) b = fmax(b, red[nw + w]);
+  }
 }
 
 // Reduce the partials of the previous launch and derive the step scalars.
-// `red` is this reduction's own LDS scratch (2 * blockDim/64 doubles).
+// `red` is this reduction's own LDS scratch (2 * blockDim/64 doubles). With
+// TWO = false the fast-speed partials (all 0) are not read.
+template <bool TWO = true>
 __device__ inline Step begin_step(const SolveDesc& sd, double* red) {
   const double* pl = sd.part + (long long)sd.par * 2 * sd.nblocks;
   const double* pc = pl + sd.nblocks;
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < sd.nblocks; i += blockDim.x) {
     a = fmax(a, pl[i]);
-    b = fmax(b, pc[i]);
+    if (TWO) b = fmax(b, pc[i]);
   }
-  block_max2_all(a, b, red);
+  block_max2_all<TWO>(a, b, red);
   const DevState* st = sd.st;
   return derive_step(st->S[sd.par], st->T, st->max_steps, st->err_word != ~0ull, a, b, sd.ph.ch_factor, sd.xi_mode,
                      sd.nu, sd.xi_fixed, sd.dx);
@@ -398,7 +416,7 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
   T f[Q][P], lo[P];
   K::load((const T*)((n0 & 1) ? sd.fb : sd.fa), xl, f);
   K::load_lo((const T*)((n0 & 1) ? sd.fb : sd.fa), xl, lo);
-  const Step S = begin_step(sd, red);
+  const Step S = begin_step<KIND == K_MHD>(sd, red);
   if (S.done) {
     carry_done(sd, S, tile);
     return;
@@ -437,7 +455,7 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
     // characteristic boundaries: the boundary cells are replaced afterwards
     if (!(sd.bcx == 2 && (x == 0 || x == N - 1))) K::new_state(sd, Un, x, n + 1, lam, cfm);
   }
-  block_max2(lam, cfm, red_end);
+  block_max2<KIND == K_MHD>(lam, cfm, red_end);
   end_step(sd, S, tile, lam, cfm);
 }
 
@@ -547,7 +565,7 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   else K::load(src, below, fbelow);
   K::load(src, y0 * nx + xl, fraw);
   K::load_lo(src, y0 * nx + xl, lo);
-  const Step S = begin_step(sd, red);
+  const Step S = begin_step<KIND == K_MHD>(sd, red);
   if (S.done) {
     carry_done(sd, S, tile);
     return;
@@ -685,7 +703,7 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   if (PARTIAL) K::template relax_one<1>(fraw[REST], fraw[4], false, sd.ph, ixi, Lam, ch, fs[4]);
   else K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
   if (x < nx) finish(y1);
-  block_max2(lam, cfm, red_end);
+  block_max2<KIND == K_MHD>(lam, cfm, red_end);
   end_step(sd, S, tile, lam, cfm);
 }
 
