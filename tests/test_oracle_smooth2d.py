@@ -2,8 +2,12 @@
 their exact solutions: the isentropic vortex converges at second order at
 omega = 2 with the weighted-upwind and the centered sets (the weighted one
 more accurate), the entropy wave too with the centered set, and the weighted
-set is much more accurate there on a coarse grid."""
+set is much more accurate there on a coarse grid. The weighted step's linear
+instability at omega = 2 about the entropy wave's background state is
+derived and checked against the oracle's own growth rate."""
 import math
+
+import numpy as np
 
 import pytest
 
@@ -53,3 +57,86 @@ def test_discontinuous_set_unstable_on_smooth_problems(oracle, prob):
                 assert r["status"] == 1 and r["steps"] < P.max_steps, (nu, r["steps"])
             else:
                 assert r["status"] == 0 and r["steps"] == P.max_steps, nu
+
+
+def _linearized_step(O, U0, nu, c, k, omega, frozen=False):
+    """Matrix C of one collision about the uniform state U0 (D2Q5, Euler):
+    delta f* = [(1 - omega) I + omega J E] delta f, with J = d f^eq / dU by
+    central differences of the oracle's equilibrium at frozen Lambda and xi
+    (or, frozen=True, with the weights held at their values at U0:
+    F^{d,+-} linearized as W^{d,+-}(U0) A^d(U0)), E the sum over populations."""
+    gamma = 1.4
+    cf = O.make_config(system="euler", dim=2, n=(8, 8), gamma=gamma, c=c, k=k)
+    Lam = 1.0 + math.sqrt(gamma)            # |u| + a of rho = p = u = v = 1
+    xi = Lam / nu
+    if frozen:
+        I4 = np.eye(4)
+        parts = []
+        for d in range(2):
+            A = O.jacobian(cf, d, U0, 0.0)
+            lam, R = np.linalg.eig(A)
+            al = 1.0 / (1.0 + np.exp(-k * lam.real / Lam))
+            Wp = (R @ np.diag(al) @ np.linalg.inv(R)).real
+            parts.append((Wp @ A, (I4 - Wp) @ A))
+        (A1p, A1m), (A2p, A2m) = parts
+        J = np.vstack([c * I4 + A1p / xi, c * I4 - A1m / xi, (1 - 4 * c) * I4 - (A1p + A2p - A1m - A2m) / xi,
+                       c * I4 + A2p / xi, c * I4 - A2m / xi])
+    else:
+        J = np.zeros((20, 4))
+        h = 1e-6
+        for j in range(4):
+            d = np.zeros(4)
+            d[j] = h
+            J[:, j] = (O.feq(cf, U0 + d, xi, 0.0, lam=Lam).reshape(-1)
+                       - O.feq(cf, U0 - d, xi, 0.0, lam=Lam).reshape(-1)) / (2 * h)
+    E = np.tile(np.eye(4), (1, 5))
+    return (1.0 - omega) * np.eye(20) + omega * J @ E, xi
+
+
+def _max_amplification(C, n):
+    """max |eig(S(theta) C)| over the Fourier modes of an n x n periodic grid,
+    S the streaming phase of the velocities (+x, -x, 0, +y, -y)."""
+    vel = [(1, 0), (-1, 0), (0, 0), (0, 1), (0, -1)]
+    best = 0.0
+    for mx in range(n):
+        for my in range(mx, n):        # symmetric in x and y
+            tx, ty = 2 * np.pi * mx / n, 2 * np.pi * my / n
+            s = np.concatenate([np.full(4, np.exp(-1j * (tx * vx + ty * vy))) for vx, vy in vel])
+            best = max(best, float(np.max(np.abs(np.linalg.eigvals(s[:, None] * C)))))
+    return best
+
+
+def test_weighted_step_unstable_about_entropy_wave_state_at_omega_two(oracle):
+    """Why the weighted entropy wave at omega = 2 grows a mode (it turns
+    non-physical after a few thousand steps): linearized about its background
+    state (rho = u = v = p = 1) the weighted step at the paper's c = 0.05,
+    k = 2, nu = 0.3 amplifies the diagonal mode theta = (2 pi/3, 2 pi/3) by
+    1.0194 per step, through the weights' dependence on U (with the weights
+    held at their background values the step is neutrally stable, as is the
+    centered set). The oracle's full nonlinear step reproduces that rate on a
+    small perturbation of the uniform state, which pins its collision,
+    streaming and moments to the linear analysis."""
+    O = oracle
+    n = 48                       # divisible by 3: theta = 2 pi / 3 is a grid mode
+    U0 = I.euler_state(np.array([1.0]), 1.0, 1.0, 1.4, v=1.0)[:, 0]
+    C, xi = _linearized_step(O, U0, 0.3, 0.05, 2.0, 2.0)
+    g_wu = _max_amplification(C, n)
+    Cf, _ = _linearized_step(O, U0, 0.3, 0.05, 2.0, 2.0, frozen=True)
+    g_frozen = _max_amplification(Cf, n)
+    nu_c = 0.3 / math.sqrt(2.5)
+    Cc, xi_c = _linearized_step(O, U0, nu_c, 0.2, 0.0, 2.0)
+    g_c = _max_amplification(Cc, n)
+    assert 1.015 < g_wu < 1.025, g_wu
+    assert abs(g_frozen - 1.0) < 1e-9 and abs(g_c - 1.0) < 1e-9, (g_frozen, g_c)
+    base = np.repeat(U0[:, None], n * n, axis=1)
+    Up = base * (1.0 + 1e-12 * np.random.default_rng(5).standard_normal(base.shape))
+    for (c, k, x, g) in ((0.05, 2.0, xi, g_wu), (0.2, 0.0, xi_c, g_c)):
+        norms = []
+        for steps in (400, 600):
+            cf = O.make_config(system="euler", dim=2, n=(n, n), gamma=1.4, c=c, k=k, omega=2.0, xi_mode="fixed",
+                               xi=x, bc=("periodic", "periodic"), max_steps=steps)
+            r = O.run(cf, Up)
+            assert r["status"] == 0
+            norms.append(np.sqrt(np.mean((r["U"] - base) ** 2)))
+        rate = (norms[1] / norms[0]) ** (1.0 / 200)
+        assert abs(rate - g) < 1e-3, (c, rate, g)
