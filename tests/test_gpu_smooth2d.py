@@ -3,7 +3,9 @@ parity with the oracle, and the paper's convergence claims against the exact
 solutions at N = 64 .. 512: second order for the vortex with the
 weighted-upwind and centered sets (weighted more accurate at every N) and
 for the entropy wave with the centered set; the weighted set an order of
-magnitude more accurate on the entropy wave's coarse grid."""
+magnitude more accurate on the entropy wave's coarse grid; and the weighted
+step's linear growth rate at omega = 2 about the entropy wave's background
+state."""
 import math
 
 import numpy as np
@@ -68,3 +70,37 @@ def test_entropy_wave_weighted_far_more_accurate_on_coarse_grid(gpu):
     c = gpu_err(gpu, I.entropy_wave_2d(64, eq_set="centered"), "wave")
     print(f"[wave 64] weighted {w:.2e} centered {c:.2e}", flush=True)
     assert w < 0.1 * c
+
+
+@pytest.mark.parametrize("prec", ["fp64"])
+def test_weighted_growth_rate_at_omega_two(gpu, oracle, prec):
+    """The weighted step's linear instability at omega = 2 about the entropy
+    wave's background state (rho = u = v = p = 1; amplification 1.0194 per
+    step at c = 0.05, k = 2, nu = 0.3) on the GPU: a 1e-12 perturbation grows
+    at that rate, and the perturbed run matches the oracle step for step."""
+    n = 48
+    U0 = I.euler_state(np.array([1.0]), 1.0, 1.0, 1.4, v=1.0)[:, 0]
+    base = np.repeat(U0[:, None], n * n, axis=1)
+    Up = base * (1.0 + 1e-12 * np.random.default_rng(5).standard_normal(base.shape))
+    xi = (1.0 + math.sqrt(1.4)) / 0.3
+    norms = []
+    for steps in (400, 600):
+        P = I.Problem(name="euler2d_uniform_perturbed", system="euler", dim=2, n=(n, n), gamma=1.4, omega=2.0,
+                      xi_mode="fixed", xi=xi, bc=("periodic", "periodic"), max_steps=steps, U0=Up)
+        s = gpu.Solver(P, precision=prec)
+        s.init()
+        U, _, nst = s.run()
+        s.close()
+        assert nst == steps
+        norms.append(np.sqrt(np.mean((U - base) ** 2)))
+        if steps == 600:
+            ref = run_oracle(oracle, P)
+            # the two sides round differently (closed-form split against the
+            # oracle's eigenvectors, ~1e-14 per step), and the growing mode
+            # amplifies that by 1.0194^600 ~ 1e5: U agrees to 1e-9, and the
+            # perturbation itself to a few per cent of its size
+            assert np.abs(U - ref["U"]).max() <= 1e-9
+            d_gpu, d_ref = U - base, ref["U"] - base
+            assert np.abs(d_gpu - d_ref).max() <= 0.05 * np.abs(d_ref).max()
+    rate = (norms[1] / norms[0]) ** (1.0 / 200)
+    assert abs(rate - 1.0194) < 1e-3, rate
