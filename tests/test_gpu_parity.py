@@ -87,7 +87,7 @@ CASES = {
     "mhd2d_riemann_fp32": (lambda: I.random_riemann("mhd", 2, 100, seed=9, max_steps=60), "fp32", {}),
     "mhd2d_ot_fp32_compensated": (lambda: I.orszag_tang(96, steps=60), "fp32", {"basis": 3}),
     "linear2d_omega17_fp64": (lambda: linear2d(70, 40, 1.7), "fp64", {}),
-    # the shallow water and Euler Riemann tables of Sec. 5.1 / 5.2 and the omega sweep of Sec. 6
+    # the shallow water and Euler Riemann tables of Sec. 5.1 / 5.2 and the omega sweep of Sec. 5.4
     "sw1d_hydraulic_fp64": (lambda: I.sw_riemann("hydraulic", 1500), "fp64", {}),
     "sw1d_hydraulic_fp32": (lambda: I.sw_riemann("hydraulic", 1500), "fp32", {}),
     "sw1d_hydraulic_centered_fp32": (lambda: I.sw_riemann("hydraulic", 1500, eq_set="centered"), "fp32", {}),

@@ -8,7 +8,7 @@ textbook theory):
   beats the centered set; the discontinuous set breaks down where an
   eigenvalue changes sign (total variation blow-up in the shallow water
   cases, a stationary jump at the sonic point of the Euler rarefactions);
-* the relaxation sweep of Sec. 6 (omega > 1 on Sod and Brio-Wu): the
+* the relaxation sweep of Sec. 5.4 (omega > 1 on Sod and Brio-Wu): the
   thresholds at which each set loses positivity;
 * the CFL limit of the discontinuous set on Brio-Wu (Sec. 5.3).
 """
@@ -190,7 +190,7 @@ def test_discontinuous_set_forms_jump_at_sonic_point(oracle, which):
 
 @pytest.mark.parametrize("eq_set,last_ok", [("weighted", 1.3), ("centered", 1.6)])
 def test_omega_sweep_brio_wu_positivity_threshold(oracle, eq_set, last_ok):
-    """Sec. 6: on Brio-Wu the centered set keeps a positive pressure up to
+    """Sec. 5.4: on Brio-Wu the centered set keeps a positive pressure up to
     omega = 1.6 and fails above it; the weighted set fails from omega = 1.4
     on (the threshold the text states)."""
     for om in (1.0, round(last_ok - 0.1, 1), last_ok):
@@ -201,7 +201,7 @@ def test_omega_sweep_brio_wu_positivity_threshold(oracle, eq_set, last_ok):
 
 
 def test_omega_sweep_sod_oscillations_grow_until_breakdown(oracle):
-    """Sec. 6 on Sod: raising omega above one grows oscillations behind the
+    """Sec. 5.4 on Sod: raising omega above one grows oscillations behind the
     shock (the exact density is non-increasing in x, so any increase is
     spurious) for both sets, and the weighted set breaks down (a
     non-physical state) by omega = 1.6; at omega = 1 both stay monotone to
@@ -226,7 +226,7 @@ def test_brio_wu_discontinuous_set_cfl_limit(oracle):
     waves only. In 1D, B_x and psi stay exactly uniform, so the cleaning speed
     enters only through Lambda, and c_h = max c_f (ch_factor = 1) gives exactly
     that reading. With the cleaning speed 6 max c_f inside Lambda (the default,
-    which reproduces the omega thresholds of Sec. 6 exactly) the physical waves
+    which reproduces the omega thresholds of Sec. 5.4 exactly) the physical waves
     run at a sixth of nu and the discontinuous set is stable at 0.9 as well."""
     for n in (400, 1600):
         for nu, ok in ((0.45, True), (0.5, False), (0.9, False)):
