@@ -174,7 +174,9 @@ vklb_status vklb_create(const vklb_system* sys, vklb_lattice lat, const vklb_gri
                         vklb_solver** out);
 
 /* Set the end condition: steps past time T (T = INFINITY: none) or past
- * max_steps (< 0: none) become no-ops. Call before vklb_init. */
+ * max_steps (< 0: none) become no-ops. Before vklb_init it is stored for the
+ * init; after it, it applies from the next vklb_step on (the call waits for
+ * the solver's stream). VKLB_ERR_ARG for T = NaN. */
 vklb_status vklb_set_end(vklb_solver* s, double T, int64_t max_steps);
 
 /* Initialization (Sec. 3.5): xi^0 and c_h^0 from U0, f_q = f_q^eq(U0), t = 0.

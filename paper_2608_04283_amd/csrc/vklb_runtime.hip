@@ -186,8 +186,10 @@ vklb_status ensure_graph(vklb_solver* s) {
   vklb_status st = launch_steps(s, s->cap_stream, s->chunk, 0);  // parities 0, 1, 0, 1, ...
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
-  if (st != VKLB_OK) return st;
-  if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
+  if (st != VKLB_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return st != VKLB_OK ? st : hip_fail(s, e, "hipStreamEndCapture");
+  }
   s->graph = g;
   HIPCHK(s, hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0));
   return VKLB_OK;
@@ -330,6 +332,22 @@ vklb_status vklb_set_end(vklb_solver* s, double T, int64_t max_steps) {
   if (isnan(T)) return fail(s, VKLB_ERR_ARG, "T is NaN");
   s->T = T;
   s->max_steps = max_steps < 0 ? (1ll << 62) : max_steps;
+  if (s->inited) {
+    // after init the device copy is updated too, in stream order: steps
+    // already queued keep the old end condition, later ones see the new one.
+    // The finished flag of the scalars the next launch reads is cleared, so a
+    // solve that had reached its old end goes on (a non-physical state still
+    // stops it: that comes from the error word).
+    HIPCHK(s, hipSetDevice(s->device));
+    char* st = s->buf + s->L.state_off;
+    const int zero = 0;
+    const size_t done_off = offsetof(DevState, S) + size_t(s->launches & 1) * sizeof(Scal) + offsetof(Scal, done);
+    HIPCHK(s, hipMemcpyAsync(st + offsetof(DevState, T), &s->T, sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(st + offsetof(DevState, max_steps), &s->max_steps, sizeof(long long),
+                             hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(st + done_off, &zero, sizeof(int), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+  }
   return VKLB_OK;
 }
 

@@ -228,6 +228,12 @@ class Solver:
             raise VklbError(r, lib().vklb_last_error(self._h).decode() or lib().vklb_status_str(r).decode())
         return r
 
+    def set_end(self, T=math.inf, max_steps=-1):
+        """End condition (vklb_set_end): time T and/or a step count; after init
+        it applies from the next step on, also to a solve that had finished."""
+        self._check(lib().vklb_set_end(self._h, float(T), int(max_steps)))
+        return self
+
     def init(self, U0=None):
         U0 = self.problem.U0 if U0 is None else U0
         U0 = np.ascontiguousarray(np.asarray(U0, dtype=np.float64).reshape(self.p, self.cells))

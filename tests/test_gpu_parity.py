@@ -301,3 +301,38 @@ def test_nonphysical_state_reported(gpu, oracle):
     s.close()
     assert d["nonphysical"] == 1 and d["fail_step"] == ref["fail_step"]
     assert d["fail_cell"] == ref["fail_cell"]
+
+
+def test_end_condition_extended_after_init(gpu, oracle):
+    """vklb_set_end after vklb_init: a step budget raised from 100 to 150
+    gives bitwise the straight 150-step run; an end time raised from 0.05 to
+    0.1 after the solve finished lands on each exactly, and (omega = 1: the
+    collision forgets everything but U) the second leg equals the oracle
+    restarted from U(0.05) for a duration of 0.05."""
+    P = I.sod(3000)
+    s = gpu.Solver(P.with_(T=math.inf, max_steps=150))
+    s.init()
+    s.step(200)
+    U150, t150, n150 = s.moments()
+    s.close()
+    s = gpu.Solver(P.with_(T=math.inf, max_steps=100))
+    s.init()
+    s.step(120)
+    _, _, n = s.moments()
+    assert n == 100
+    s.set_end(math.inf, 150)
+    s.step(80)
+    U, t, n = s.moments()
+    s.close()
+    assert n == n150 == 150 and t == t150 and np.array_equal(U, U150)
+    s = gpu.Solver(P.with_(T=0.05))
+    s.init()
+    U1, t1, n1 = s.run()
+    assert t1 == 0.05
+    s.set_end(0.1, -1)
+    U2, t2, n2 = s.run()
+    s.close()
+    assert t2 == 0.1 and n2 > n1
+    ref = run_oracle(oracle, P.with_(T=0.05, U0=U1))
+    assert n2 - n1 == ref["steps"]
+    assert np.all(rel_l1(U2, ref["U"]) <= 1e-12)
