@@ -160,3 +160,26 @@ def test_product_path_never_loads_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 for bad in ("import oracle", "from oracle", "oracle/", "oracle.py", "liboracle", "vklb_oracle"):
                     assert bad not in txt, (f, bad)
+
+
+def test_plain_c_program_uses_the_abi(vk, tmp_path):
+    """include/vklb.h is valid C99 (compiled with -pedantic, warnings as
+    errors), and a C program linked against the library gets the same
+    answers as the binding for the calls that need no GPU."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lib_dir = os.path.dirname(vk.LIB_PATH)
+    exe = str(tmp_path / "abi_check")
+    subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "c", "abi_check.c"), "-L", lib_dir, "-lvklb",
+                    "-Wl,-rpath," + lib_dir, "-o", exe], check=True)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True, timeout=60).stdout.splitlines()
+    got = dict(line.split(" ", 1) for line in out)
+    assert got["status"] == "non-physical state"
+    assert int(got["workspace_fp64"]) == vk.workspace_bytes(I.sod(65536), "fp64")
+    code, msg = got["create_bad_omega"].split(" ", 1)
+    assert int(code) == vk.ERR_ARG and "omega" in msg
+    assert got["solver_null"] == "1"
