@@ -10,6 +10,7 @@ import pytest
 
 from paper_2608_04283_amd import inputs as I
 from exact_riemann import EulerRiemann, ShallowWaterRiemann, cell_average_exact
+from parity_util import run_oracle
 
 
 def cfg_of(O, P, **kw):
@@ -361,3 +362,18 @@ def test_paper_standard_dam_break_wu_beats_centered(oracle):
         hu = cell_average_exact(sampler, np.linspace(-5, 5, n + 1), r["t"], 0.0, sub=4)
         errs[name] = np.abs(r["U"][0] - hu[0]).mean()
     assert errs["wu"] < errs["centered"]
+
+
+def test_paper_orszag_tang_reading(oracle):
+    """Sec. 5.3, Orszag-Tang: read with rho = 25/9, p = 5/3 (the printed
+    values scaled by 4 pi, as unit-amplitude u and B require), the weighted
+    set with c = 0 that the paper shows at T = 0.5 gets there; read
+    literally (rho = 25/(36 pi), p = 5/(12 pi)) it turns non-physical before
+    t = 0.1."""
+    O = oracle
+    r = run_oracle(O, I.orszag_tang_paper(64, c=0.0))
+    assert r["status"] == 0 and abs(r["t"] - 0.5) < 1e-12
+    lit = I.orszag_tang(64, steps=2**62, gamma=5.0 / 3.0, rho0=25.0 / (36.0 * math.pi), p0=5.0 / (12.0 * math.pi),
+                        T=0.5, c=0.0)
+    r = run_oracle(O, lit)
+    assert r["status"] == 1 and r["t"] < 0.1
