@@ -377,3 +377,27 @@ def test_paper_orszag_tang_reading(oracle):
                         T=0.5, c=0.0)
     r = run_oracle(O, lit)
     assert r["status"] == 1 and r["t"] < 0.1
+
+
+@pytest.mark.parametrize("nu", [0.3, 0.6, 0.9])
+def test_monotone_bound_on_c(oracle, nu):
+    """Sec. 4.2: with the discontinuous split (k -> infinity) and a constant
+    Jacobian (linear advection, a > 0, so F+ = aU and F- = 0), one omega = 1
+    step is the three-point update with weights c + nu (upwind neighbour),
+    1 - 2c - nu (the cell) and c (downwind neighbour): monotone exactly when
+    0 <= c <= (1 - nu)/2. A one-cell spike shows the weights; just above the
+    bound the cell's own weight is negative and the spike turns into an
+    undershoot."""
+    O = oracle
+    n, j = 32, 16
+    U0 = np.zeros(n)
+    U0[j] = 1.0
+    for c, monotone in (((1.0 - nu) / 2.0, True), ((1.0 - nu) / 2.0 + 0.02, False)):
+        cf = O.make_config(system="linear", dim=1, n=(n, 1), adv=(1.0, 0.0), nu=nu, c=c, k=math.inf, omega=1.0,
+                           bc=("periodic", "periodic"), max_steps=1)
+        r = O.run(cf, U0.reshape(1, n))
+        U = r["U"][0]
+        assert U[j - 1] == pytest.approx(c, abs=1e-15)
+        assert U[j] == pytest.approx(1.0 - 2.0 * c - nu, abs=1e-14)
+        assert U[j + 1] == pytest.approx(c + nu, abs=1e-14)
+        assert (U.min() >= -1e-15) == monotone, (c, U.min())
