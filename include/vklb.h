@@ -134,7 +134,7 @@ typedef struct {
                        0: default: FP64 -> 1; FP32 -> 3 in 1D, 2 in 2D.
                        Other values: VKLB_ERR_ARG. */
   int band_rows;    /* 2D: rows per workgroup band (8..64); 0 = tuned default */
-  int graph_chunk;  /* steps captured per HIP graph (0 = 64; < 0: plain launches) */
+  int graph_chunk;  /* steps captured per HIP graph (0 = 512; < 0: plain launches) */
   int strip_width;  /* 2D: columns per workgroup (64, 128 or 256); 1D: lanes per workgroup
                        (256 or 512, each finishing W - 2 cells); 0 = tuned default */
   int halo_rows;    /* 2D: rows of the two halo columns collided per batch (1..32); 0 = tuned default */

@@ -317,7 +317,7 @@ vklb_status vklb_create(const vklb_system* sys, vklb_lattice lat, const vklb_gri
   int band = s->opt.band_rows;
   if (band < 1) band = default_band(sys->kind);
   if (band > 4096) band = 4096;
-  s->chunk = s->opt.graph_chunk == 0 ? 64 : s->opt.graph_chunk;
+  s->chunk = s->opt.graph_chunk == 0 ? 512 : s->opt.graph_chunk;  // 512: 1-2% per 1D step over 64
   if (s->chunk > 0) s->chunk = (s->chunk + 1) / 2 * 2;  // even: replays start on parity 0
   int halo = s->opt.halo_rows;
   if (halo < 1 || halo > 32) halo = default_halo(sys->kind);
