@@ -17,13 +17,15 @@
 //     (A - lambda I) (Sec. 2.2, eigen-decomposition of the flux Jacobian),
 //   * expansion coefficients Phi = P^{-1} F by an LU solve (Sec. 2.2,
 //     expansion coefficients),
-//   * sigmoid weights alpha(lambda) = 1/(1+exp(-k lambda/max_j|lambda_j|))
-//     and the weighted partial fluxes (Sec. 3.1, weighted upwind splitting),
+//   * sigmoid weights alpha(lambda) = 1/(1+exp(-k lambda/Lambda)) and the
+//     weighted partial fluxes (Sec. 3.1, weighted upwind splitting); Lambda is
+//     the global max |lambda| of the state (or, as an option, the cell's own),
 //   * the WU equilibrium in 1D (Sec. 3.1, f1..f3) and 2D (Sec. 3.4, D2Q5 set),
 //   * collision, streaming, moment recovery and the CFL speed update in the
 //     order of the flow chart of Sec. 3.5.
-// Readings where the paper is silent (boundary ghosts, end-time landing,
-// local lambda_max, global c_h) are listed in the design doc and noted inline.
+// Where the paper is silent (boundary ghosts, the end-time landing step, the
+// normalization Lambda of the weights, a global c_h) the reading taken is
+// stated inline where it is used.
 #include <cmath>
 #include <complex>
 #include <cstdint>
