@@ -376,21 +376,24 @@ struct Kern {
     relax(f, ph, ixi, Lam, ch, fs, U);
   }
 
-  // Speeds of a finished cell for the global maxima; flags non-physical states.
-  __device__ static inline void new_state(const SolveDesc& sd, const T (&U)[P], long long cell, long long step,
+  // Speeds of a finished cell for the global maxima; flags non-physical
+  // states (the error word, and the return value).
+  __device__ static inline bool new_state(const SolveDesc& sd, const T (&U)[P], long long cell, long long step,
                                           double& lam, double& cfm) {
     ST Us[P];
 #pragma unroll
     for (int v = 0; v < P; ++v) Us[v] = ST(U[v]);
     ST l, c;
     Cell<KIND, DIM, ST>::speeds(Us, sd.ph, &l, &c);
-    if (!Cell<KIND, DIM, ST>::admissible(Us, sd.ph)) {
+    const bool bad = !Cell<KIND, DIM, ST>::admissible(Us, sd.ph);
+    if (bad) {
       atomicMin(&sd.st->err_word, ((unsigned long long)step << 32) | (unsigned long long)cell);
       l = ST(0);
       c = ST(0);
     }
     lam = fmax(lam, double(l));
     cfm = fmax(cfm, double(c));
+    return bad;
   }
 };
 
@@ -457,6 +460,149 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
   }
   block_max2<KIND == K_MHD>(lam, cfm, red_end);
   end_step(sd, S, tile, lam, cfm);
+}
+
+// ---------------------------------------------------------------------------
+// Small 1D grids (N <= B R cells): one workgroup of B lanes runs `count`
+// whole steps in a loop, lane tid holding cells r * B + tid (r < R) in
+// registers. The workgroup barrier is the global synchronization, so the
+// steps need no launches: a step costs its arithmetic and three barriers
+// instead of a launch. Every cell value and maximum comes from the same code
+// as step1d_tile (and the max is exact), so the results are bitwise those of
+// `count` step launches, and the kernel leaves the scalars, partials and
+// populations as those launches would (parity sd.par ^ (count & 1)).
+// ---------------------------------------------------------------------------
+template <int KIND, class T, int BASIS, int R, int B>
+__global__ void __launch_bounds__(B) k_run1d_wg(const SolveDesc sd, int count) {
+  using K = Kern<KIND, 1, T, BASIS>;
+  constexpr bool DELTA = K::DELTA;
+  constexpr bool MHD = KIND == K_MHD;
+  constexpr int P = K::P, Q = 3;
+  __shared__ T s_plus[P][B * R], s_minus[P][B * R];
+  __shared__ double red[2 * (B / 64) + 2];
+  const int N = sd.nx;
+  const int tid = threadIdx.x;
+  DevState* st = sd.st;
+  // scalars and maxima left by the previous launch (parity sd.par)
+  const Scal s0 = st->S[sd.par];
+  double t = s0.t;
+  long long n = s0.n;
+  int done = s0.done;
+  bool err = st->err_word != ~0ull;
+  double lam = 0.0, cfm = 0.0;
+  {
+    const double* pl = sd.part + (long long)sd.par * 2 * sd.nblocks;
+    for (int i = tid; i < sd.nblocks; i += B) {
+      lam = fmax(lam, pl[i]);
+      if (MHD) cfm = fmax(cfm, pl[sd.nblocks + i]);
+    }
+    block_max2_all<MHD>(lam, cfm, red);
+  }
+  T f[R][Q][P], lo[R][P];
+  {
+    const T* __restrict__ src = (const T*)((n & 1) ? sd.fb : sd.fa);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int c = r * B + tid;
+      if (c < N) {
+        K::load(src, c, f[r]);
+        K::load_lo(src, c, lo[r]);
+      }
+    }
+  }
+  const int left_ghost = sd.bcx == 0 ? N - 1 : 0, right_ghost = sd.bcx == 0 ? 0 : N - 1;
+  for (int it = 0; it < count; ++it) {
+    Scal sc;
+    sc.t = t;
+    sc.n = n;
+    sc.done = done;
+    sc.pad = 0;
+    const Step S = derive_step(sc, st->T, st->max_steps, err, lam, cfm, sd.ph.ch_factor, sd.xi_mode, sd.nu,
+                               sd.xi_fixed, sd.dx);
+    if (S.done) {
+      done = 1;
+      break;
+    }
+    const double ixi = 1.0 / S.xi;
+    T fs[R][Q][P], U[R][P];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int c = r * B + tid;
+      if (c < N) {
+        K::relax(f[r], sd.ph, ixi, S.lam, S.ch, fs[r], U[r]);
+#pragma unroll
+        for (int v = 0; v < P; ++v) {
+          s_plus[v][c] = fs[r][0][v];
+          s_minus[v][c] = fs[r][2][v];
+        }
+      }
+    }
+    __syncthreads();
+    double lm = 0.0, cm = 0.0;
+    int bad = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int c = r * B + tid;
+      if (c < N) {
+        const int cl = c > 0 ? c - 1 : left_ghost, cr = c < N - 1 ? c + 1 : right_ghost;
+        T Un[P];
+#pragma unroll
+        for (int v = 0; v < P; ++v) {
+          const T a = s_plus[v][cl];
+          const T b = s_minus[v][cr];
+          if (DELTA) {
+            T lo_new;
+            Un[v] = K::advance(U[r][v], (a - fs[r][0][v]) + (b - fs[r][2][v]), lo[r][v], lo_new);
+            f[r][1][v] = Un[v];
+            if (K::COMP) lo[r][v] = lo_new;
+          } else {
+            f[r][1][v] = fs[r][1][v];
+            Un[v] = ((T(0) + a) + fs[r][1][v]) + b;
+          }
+          f[r][0][v] = a;
+          f[r][2][v] = b;
+        }
+        bad |= K::new_state(sd, Un, c, S.n + 1, lm, cm) ? 1 : 0;
+      }
+    }
+    // the barriers inside keep the LDS arrays and `red` from being rewritten
+    // by the next step while a lane still reads them
+    err = __syncthreads_or(bad) != 0 || err;
+    block_max2_all<MHD>(lm, cm, red);
+    lam = lm;
+    cfm = cm;
+    t = S.landing ? st->T : S.t + sd.dx / S.xi;
+    n = S.n + 1;
+  }
+  T* __restrict__ dst = (T*)((n & 1) ? sd.fb : sd.fa);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int c = r * B + tid;
+    if (c < N) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int v = 0; v < P; ++v) dst[K::pidx(q * P + v, c)] = f[r][q][v];
+      if (K::COMP) {
+#pragma unroll
+        for (int v = 0; v < P; ++v) dst[K::pidx(Q * P + v, c)] = lo[r][v];
+      }
+    }
+  }
+  const int pf = sd.par ^ (count & 1);
+  double* pl = sd.part + (long long)pf * 2 * sd.nblocks;
+  for (int i = tid; i < sd.nblocks; i += B) {
+    pl[i] = lam;
+    pl[sd.nblocks + i] = cfm;
+  }
+  if (tid == 0) {
+    Scal o;
+    o.t = t;
+    o.n = n;
+    o.done = done;
+    o.pad = 0;
+    st->S[pf] = o;
+  }
 }
 
 // Characteristic (non-reflecting) boundaries of Sec. 3.3, 1D, launched after

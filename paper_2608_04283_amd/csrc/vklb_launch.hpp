@@ -8,6 +8,7 @@
 namespace vklb {
 
 typedef hipError_t (*launch_fn)(const SolveDesc&, int grid, hipStream_t);
+typedef hipError_t (*wg_fn)(const SolveDesc&, int count, int cells_per_lane, int lanes, hipStream_t);
 typedef hipError_t (*batched_fn)(const SolveDesc* descs, const WorkItem* work, const int* nwork, int par, int grid,
                                  hipStream_t);
 
@@ -17,7 +18,9 @@ struct Launchers {
   launch_fn step = nullptr;
   launch_fn moments = nullptr;
   batched_fn batched = nullptr;  // serving: tiles of many solves in one launch
-  launch_fn char_bc = nullptr;   // 1D characteristic boundaries (SW, Euler, linear)
+  launch_fn char_bc = nullptr;   // 1D characteristic boundaries
+  wg_fn run_wg = nullptr;        // 1D grids of up to wg_max_cells: many steps in one workgroup
+  int wg_max_cells = 0;
   int block = 256;  // threads per step workgroup
 };
 

@@ -130,6 +130,8 @@ struct vklb_solver {
   int device = 0;
   int basis = 0;
   long long launches = 0;   // step launches since init (selects the parity)
+  int wg_cells = 0;         // > 0: 1D steps run in one workgroup, this many cells per lane
+  int wg_lanes = 0;         // and this many lanes
 };
 
 namespace {
@@ -323,6 +325,19 @@ vklb_status vklb_create(const vklb_system* sys, vklb_lattice lat, const vklb_gri
   if (halo < 1 || halo > 32) halo = default_halo(sys->kind);
   s->sd = make_desc(s->buf, L, sys, &s->grid, lambda, omega, s->bc, eq, width, band, halo);
   s->step_grid = s->sd.nblocks;
+  // small 1D grids: whole step sequences in one workgroup (bitwise the same)
+  if (grid->dim == 1 && s->sd.bcx != 2 && s->opt.small_grid >= 0 && s->K.run_wg && grid->n[0] <= s->K.wg_max_cells) {
+    const long long n = grid->n[0];
+    // 512 lanes measured fastest for every N <= 1024 (1 or 2 cells per lane);
+    // MHD holds too many registers for more than 256 lanes of one cell each
+    int lanes = s->opt.small_grid;
+    if (lanes != 256 && lanes != 512 && lanes != 1024) lanes = 512;
+    if (sys->kind == VKLB_MHD_GLM) lanes = 256;
+    int cells = int((n + lanes - 1) / lanes);
+    if (cells == 3) cells = 4;
+    s->wg_lanes = lanes;
+    s->wg_cells = cells;
+  }
   *out = s;
   return VKLB_OK;
 }
@@ -385,7 +400,18 @@ vklb_status vklb_step(vklb_solver* s, int64_t n) {
   HIPCHK(s, hipEventRecord(s->ev0, s->stream));
   long long rem = n;
   vklb_status st;
-  if (s->chunk > 0 && n >= s->chunk + 1) {
+  if (s->wg_cells > 0) {
+    // each launch stands for `count` step launches (it leaves their parity)
+    while (rem > 0) {
+      const int count = int(std::min<long long>(rem, 1024));
+      SolveDesc d = s->sd;
+      d.par = int(s->launches & 1);
+      HIPCHK(s, s->K.run_wg(d, count, s->wg_cells, s->wg_lanes, s->stream));
+      s->launches += count;
+      rem -= count;
+    }
+  }
+  if (s->chunk > 0 && rem >= s->chunk + 1) {
     st = ensure_graph(s);
     if (st != VKLB_OK) return st;
     if (s->launches & 1) {  // the graph starts on parity 0

@@ -285,13 +285,15 @@ def test_checkpoint_resume_is_exact(gpu, dim, basis):
     d.close()
 
 
-def test_nonphysical_state_reported(gpu, oracle):
+@pytest.mark.parametrize("small_grid", [0, -1])
+def test_nonphysical_state_reported(gpu, oracle, small_grid):
     """Far past the omega threshold of Sec. 5.4 the Sod tube fails; the device
-    flags it and the synchronizing call returns VKLB_ERR_NONPHYSICAL."""
+    flags it and the synchronizing call returns VKLB_ERR_NONPHYSICAL (with the
+    200-cell grid run in one workgroup, and with one launch per step)."""
     P = I.sod(200, omega=1.95)
     ref = run_oracle(oracle, P)
     assert ref["status"] == 1
-    s = gpu.Solver(P, precision="fp64")
+    s = gpu.Solver(P, precision="fp64", small_grid=small_grid)
     s.init()
     s.step(5000)
     with pytest.raises(gpu.VklbError) as ei:
@@ -336,3 +338,64 @@ def test_end_condition_extended_after_init(gpu, oracle):
     ref = run_oracle(oracle, P.with_(T=0.05, U0=U1))
     assert n2 - n1 == ref["steps"]
     assert np.all(rel_l1(U2, ref["U"]) <= 1e-12)
+
+
+SMALL = {
+    # name: (problem factory, precision, options); N <= 1024 (256 for MHD) runs in one workgroup
+    "sw_dambreak_1000_fp64": (lambda: I.dam_break(1000), "fp64", {}),
+    "sw_dambreak_1000_100steps_fp32_delta": (lambda: I.dam_break(1000, max_steps=100), "fp32", {"basis": 2}),
+    "euler_sod_700_fp32_compensated": (lambda: I.sod(700), "fp32", {}),
+    "euler_sod_513_periodic_fp32_plain": (lambda: I.sod(513, bc=("periodic", "periodic")), "fp32", {"basis": 1}),
+    "euler_wave_256_fp64_two_launches": (lambda: I.smooth_wave(256), "fp64", {}),
+    "euler_sod_300_centered_fp64": (lambda: I.sod(300, eq_set="centered"), "fp64", {}),
+    "sw_riemann_500_omega13_fp64": (lambda: I.random_riemann("sw", 1, 500, seed=5, omega=1.3, max_steps=300, nu=0.5),
+                                   "fp64", {}),
+    "mhd_briowu_200_fp32": (lambda: I.brio_wu(200), "fp32", {}),
+    "mhd_briowu_256_fp64": (lambda: I.brio_wu(256), "fp64", {}),
+    "linear_300_periodic_fp64": (lambda: linear1d(300, 0.7, 2.0, 1500, "periodic"), "fp64", {}),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_small_grid_path_is_bitwise_the_launch_path(gpu, name):
+    """Small 1D grids run whole step sequences in one workgroup; the result
+    (U, t, steps) is bitwise that of one launch per step, across parities,
+    several launches of up to 1024 steps, bases, boundaries and end
+    conditions."""
+    factory, prec, opts = SMALL[name]
+    P = factory()
+    print(f"[case] {name} n={P.n} prec={prec}", flush=True)
+    out = {}
+    for sg in (-1, 0, 256, 1024):   # launches; the default 512 lanes; 256 and 1024 lanes
+        s = gpu.Solver(P, precision=prec, small_grid=sg, **opts)
+        s.init()
+        out[sg] = s.run()
+        s.close()
+    U1, t1, n1 = out[-1]
+    for sg in (0, 256, 1024):
+        U0, t0, n0 = out[sg]
+        assert n0 == n1 and t0 == t1 and np.array_equal(U0, U1), sg
+
+
+def test_small_grid_state_hands_over_to_the_launch_path(gpu):
+    """The one-workgroup kernel leaves scalars, partial maxima and populations
+    as step launches would: 301 steps in it, a checkpoint restored into a
+    solver that launches per step, and 200 more steps there give bitwise the
+    501-step run of the one-workgroup path."""
+    P = I.sod(800, T=math.inf, max_steps=2**62)
+    a = gpu.Solver(P, precision="fp32", small_grid=0)
+    a.init()
+    a.step(501)
+    U_ref, t_ref, n_ref = a.moments()
+    a.close()
+    b = gpu.Solver(P, precision="fp32", small_grid=0)
+    b.init()
+    b.step(301)
+    state, _, _ = b.get_state()
+    b.close()
+    c = gpu.Solver(P, precision="fp32", small_grid=-1)
+    c.set_state(state)
+    c.step(200)
+    U, t, n = c.moments()
+    c.close()
+    assert n == n_ref == 501 and t == t_ref and np.array_equal(U, U_ref)
