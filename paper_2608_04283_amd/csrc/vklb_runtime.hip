@@ -594,6 +594,15 @@ vklb_status vklb_tune(const vklb_system* sys, vklb_lattice lat, const vklb_grid*
       o.strip_width = w;
       cand.push_back(o);
     }
+    // grids that run in one workgroup: its lane count (MHD has one shape)
+    if (grid->n[0] <= 1024 && sys->kind != VKLB_MHD_GLM && b0.small_grid >= 0) {
+      cand.clear();
+      for (int lanes : {256, 512, 1024}) {
+        vklb_options o = b0;
+        o.small_grid = lanes;
+        cand.push_back(o);
+      }
+    }
   } else {
     const long long nx = grid->n[0], ny = grid->n[1];
     for (int w : {64, 128, 256}) {

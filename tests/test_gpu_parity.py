@@ -169,21 +169,28 @@ def test_centered_preset_equals_its_weighted_parameters(gpu, dim):
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]
 
 
-@pytest.mark.parametrize("dim", [1, 2])
+@pytest.mark.parametrize("dim", [1, 2, "1small"])
 def test_autotuner_shape_gives_identical_results(gpu, dim):
     """vklb_tune times the candidate tile shapes and returns the fastest; the
-    chosen shape reproduces the default shape's results bit for bit."""
-    P = rect_quadrants(300, 170, 5, 25) if dim == 2 else I.sod(3000, max_steps=300)
+    chosen shape reproduces the default shape's results bit for bit (for a
+    grid small enough to run in one workgroup the candidates are its lane
+    counts)."""
+    if dim == 2:
+        P = rect_quadrants(300, 170, 5, 25)
+    else:
+        P = I.sod(3000 if dim == 1 else 700, max_steps=300)
     opts, us = gpu.tune(P, "fp32", steps=10)
     print(f"[tune] dim={dim} {opts} {us:.2f} us/step", flush=True)
     assert us > 0
     if dim == 1:
         assert opts["strip_width"] in (256, 512)
+    elif dim == "1small":
+        assert opts["small_grid"] in (256, 512, 1024)
     else:
         assert opts["strip_width"] in (64, 128, 256) and opts["band_rows"] in (4, 8, 16, 32, 64)
         assert opts["halo_rows"] in (2, 8)
     outs = []
-    for kw in ({}, {k: opts[k] for k in ("strip_width", "band_rows", "halo_rows")}):
+    for kw in ({}, {k: opts[k] for k in ("strip_width", "band_rows", "halo_rows", "small_grid")}):
         s = gpu.Solver(P, precision="fp32", **kw)
         s.init()
         outs.append(s.run())
