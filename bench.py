@@ -81,11 +81,11 @@ def profiled_traffic(workload, prec, cells_per_launch):
 
 def step_kernel(P, steps):
     """The kernel that advances the workload and the steps one launch takes:
-    1D grids of up to 1024 cells (256 for MHD) without characteristic
-    boundaries run up to 1024 steps per launch in one workgroup
+    1D grids of up to 1024 cells (256 for MHD) run up to 1024 steps per
+    launch in one workgroup
     (k_run1d_wg, the library's rule for its default options); everything else
     launches k_step1d / k_step2d once per step."""
-    if P.dim == 1 and P.bc[0] != "characteristic" and P.cells <= (256 if P.system == "mhd" else 1024):
+    if P.dim == 1 and P.cells <= (256 if P.system == "mhd" else 1024):
         return "k_run1d_wg", min(1024, steps)
     return f"k_step{P.dim}d", 1
 

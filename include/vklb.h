@@ -138,7 +138,7 @@ typedef struct {
   int strip_width;  /* 2D: columns per workgroup (64, 128 or 256); 1D: lanes per workgroup
                        (256 or 512, each finishing W - 2 cells); 0 = tuned default */
   int halo_rows;    /* 2D: rows of the two halo columns collided per batch (1..32); 0 = tuned default */
-  int small_grid;   /* 1D grids of up to 1024 cells (256 for MHD) without characteristic boundaries
+  int small_grid;   /* 1D grids of up to 1024 cells (256 for MHD), any boundary condition,
                        run up to 1024 steps per launch in one workgroup, with bitwise the same
                        results as one launch per step: 0 = on, 512 lanes (256 for MHD), the fastest
                        measured; 256, 512 or 1024 = on with that many lanes; -1 = off */

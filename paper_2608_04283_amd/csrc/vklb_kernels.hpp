@@ -475,10 +475,12 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
 template <int KIND, class T, int BASIS, int R, int B>
 __global__ void __launch_bounds__(B) k_run1d_wg(const SolveDesc sd, int count) {
   using K = Kern<KIND, 1, T, BASIS>;
+  using ST = typename K::ST;
   constexpr bool DELTA = K::DELTA;
   constexpr bool MHD = KIND == K_MHD;
   constexpr int P = K::P, Q = 3;
   __shared__ T s_plus[P][B * R], s_minus[P][B * R];
+  __shared__ T s_unb[2][P];   // characteristic boundaries: U^n of cells 1 and N - 2
   __shared__ double red[2 * (B / 64) + 2];
   const int N = sd.nx;
   const int tid = threadIdx.x;
@@ -511,6 +513,7 @@ __global__ void __launch_bounds__(B) k_run1d_wg(const SolveDesc sd, int count) {
     }
   }
   const int left_ghost = sd.bcx == 0 ? N - 1 : 0, right_ghost = sd.bcx == 0 ? 0 : N - 1;
+  const bool charbc = sd.bcx == 2;
   for (int it = 0; it < count; ++it) {
     Scal sc;
     sc.t = t;
@@ -534,6 +537,14 @@ __global__ void __launch_bounds__(B) k_run1d_wg(const SolveDesc sd, int count) {
         for (int v = 0; v < P; ++v) {
           s_plus[v][c] = fs[r][0][v];
           s_minus[v][c] = fs[r][2][v];
+        }
+        if (charbc && c == 1) {
+#pragma unroll
+          for (int v = 0; v < P; ++v) s_unb[0][v] = U[r][v];
+        }
+        if (charbc && c == N - 2) {
+#pragma unroll
+          for (int v = 0; v < P; ++v) s_unb[1][v] = U[r][v];
         }
       }
     }
@@ -561,6 +572,34 @@ __global__ void __launch_bounds__(B) k_run1d_wg(const SolveDesc sd, int count) {
           }
           f[r][0][v] = a;
           f[r][2][v] = b;
+        }
+        if (charbc && (c == 0 || c == N - 1)) {
+          // characteristic boundary (Sec. 3.3), as k_char_bc1d does it after a
+          // step launch: from U^n of the cell and of its interior neighbour,
+          // U_b^{n+1} = U_b - P (Lambda dW)' / xi, populations f^eq(U_b^{n+1})
+          const int side = c == 0 ? 0 : 1;
+          ST us[P], du[P], corr[P], unew[P];
+#pragma unroll
+          for (int v = 0; v < P; ++v) {
+            us[v] = ST(U[r][v]);
+            const ST nb = ST(s_unb[side][v]);
+            du[v] = side == 1 ? ST(U[r][v]) - nb : nb - ST(U[r][v]);
+          }
+          Cell<KIND, 1, ST>::char_correction(us, du, sd.ph, ST(S.ch), side == 1, corr);
+#pragma unroll
+          for (int v = 0; v < P; ++v) unew[v] = us[v] - corr[v] * ST(ixi);
+          ST fe[Q][P];
+          Equilibrium<KIND, 1, ST>::eval(unew, sd.ph, ST(ixi), ST(S.lam), ST(S.ch), fe);
+#pragma unroll
+          for (int v = 0; v < P; ++v) Un[v] = T(unew[v]);
+#pragma unroll
+          for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int v = 0; v < P; ++v) f[r][q][v] = (DELTA && q == K::REST) ? Un[v] : T(fe[q][v]);
+          if (K::COMP) {
+#pragma unroll
+            for (int v = 0; v < P; ++v) lo[r][v] = T(0);
+          }
         }
         bad |= K::new_state(sd, Un, c, S.n + 1, lm, cm) ? 1 : 0;
       }

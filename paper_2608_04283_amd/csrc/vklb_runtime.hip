@@ -326,7 +326,7 @@ vklb_status vklb_create(const vklb_system* sys, vklb_lattice lat, const vklb_gri
   s->sd = make_desc(s->buf, L, sys, &s->grid, lambda, omega, s->bc, eq, width, band, halo);
   s->step_grid = s->sd.nblocks;
   // small 1D grids: whole step sequences in one workgroup (bitwise the same)
-  if (grid->dim == 1 && s->sd.bcx != 2 && s->opt.small_grid >= 0 && s->K.run_wg && grid->n[0] <= s->K.wg_max_cells) {
+  if (grid->dim == 1 && s->opt.small_grid >= 0 && s->K.run_wg && grid->n[0] <= s->K.wg_max_cells) {
     const long long n = grid->n[0];
     // 512 lanes measured fastest for every N <= 1024 (1 or 2 cells per lane);
     // MHD holds too many registers for more than 256 lanes of one cell each

@@ -360,6 +360,17 @@ SMALL = {
     "mhd_briowu_200_fp32": (lambda: I.brio_wu(200), "fp32", {}),
     "mhd_briowu_256_fp64": (lambda: I.brio_wu(256), "fp64", {}),
     "linear_300_periodic_fp64": (lambda: linear1d(300, 0.7, 2.0, 1500, "periodic"), "fp64", {}),
+    # characteristic boundaries (Sec. 3.3) inside the one-workgroup loop
+    "euler_sod_500_char_fp64": (lambda: I.sod(500, bc=("characteristic", "characteristic"), T=0.3), "fp64", {}),
+    "euler_sod_500_char_fp32": (lambda: I.sod(500, bc=("characteristic", "characteristic"), T=0.3), "fp32", {}),
+    "euler_pulse_400_char_fp32_delta": (lambda: acoustic_pulse(400, 0.0, 1.0, 0.6), "fp32", {"basis": 2}),
+    "sw_dambreak_1000_char_fp64": (lambda: I.dam_break(1000, bc=("characteristic", "characteristic"), T=0.2), "fp64",
+                                   {}),
+    "linear_300_char_outflow_fp64": (lambda: linear1d(300, 0.7, 2.0, 400, "characteristic"), "fp64", {}),
+    "linear_300_char_inflow_fp64": (lambda: linear1d(300, -0.7, 2.0, 400, "characteristic"), "fp64", {}),
+    "mhd_briowu_256_char_fp32": (lambda: I.brio_wu(256, T=0.3, bc=("characteristic", "characteristic")), "fp32", {}),
+    "mhd_briowu_256_char_fp64": (lambda: I.brio_wu(256, T=0.3, bc=("characteristic", "characteristic")), "fp64", {}),
+    "euler_sod_2_char_fp64": (lambda: I.sod(2, bc=("characteristic", "characteristic"), max_steps=20), "fp64", {}),
 }
 
 
