@@ -68,11 +68,12 @@ struct SolveDesc {
   int band;              // 2D rows per band
   int par;               // launch parity
   int halo;              // 2D rows of halo columns collided per batch (1..32)
+  int npar;              // parity of the step index at launches of parity 0
 };
 
 // Values every workgroup derives at the start of a step.
 struct Step {
-  double t, xi, lam, ch;
+  double t, xi, lam, ch, T;
   long long n;
   int landing, done;
 };
@@ -87,6 +88,7 @@ __host__ __device__ inline Step derive_step(const Scal& S, double T, long long m
   Step r;
   r.t = S.t;
   r.n = S.n;
+  r.T = T;
   r.ch = ch_factor > 0.0 ? ch_factor * cfm : 0.0;
   r.lam = fmax(lam7, r.ch);
   r.xi = xi_mode == 0 ? r.lam / nu : xi_fixed;
@@ -149,14 +151,15 @@ __device__ inline double wave_max(double v) {
   return __longlong_as_double((long long)(((unsigned long long)hm << 32) | lm));
 }
 
-// Block max of (a, b) into lane 0 of wave 0; `red` needs 2 * (blockDim/64)
-// doubles. TWO = false (systems without a cleaning speed, whose fast-speed
-// maxima are identically 0) reduces a alone and leaves b as it is.
+// Block max of (a, b) into lane 0 of wave 0 for a workgroup of `lanes`
+// lanes; `red` needs 2 * (lanes/64) doubles. TWO = false (systems without a
+// cleaning speed, whose fast-speed maxima are identically 0) reduces a alone
+// and leaves b as it is.
 template <bool TWO = true>
-__device__ inline void block_max2(double& a, double& b, double* red) {
+__device__ inline void block_max2(double& a, double& b, double* red, int lanes) {
   a = wave_max(a);
   if (TWO) b = wave_max(b);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = lanes >> 6;
   if (lane == 0) {
     red[wid] = a;
     if (TWO) red[nw + wid] = b;
@@ -170,13 +173,13 @@ __device__ inline void block_max2(double& a, double& b, double* red) {
   }
 }
 
-// Block max of (a, b) broadcast to every lane; `red` needs 2 * (blockDim/64)
+// Block max of (a, b) broadcast to every lane; `red` needs 2 * (lanes/64)
 // doubles and is not written again by this workgroup (no trailing barrier).
 template <bool TWO = true>
-__device__ inline void block_max2_all(double& a, double& b, double* red) {
+__device__ inline void block_max2_all(double& a, double& b, double* red, int lanes) {
   a = wave_max(a);
   if (TWO) b = wave_max(b);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = lanes >> 6;
   if (lane == 0) {
     red[wid] = a;
     if (TWO) red[nw + wid] = b;
@@ -188,23 +191,70 @@ __device__ inline void block_max2_all(double& a, double& b, double* red) {
   }
 }
 
-// Reduce the partials of the previous launch and derive the step scalars.
-// `red` is this reduction's own LDS scratch (2 * blockDim/64 doubles). With
-// TWO = false the fast-speed partials (all 0) are not read.
+// Solve state a step reads, loaded once at the start of a launch so that no
+// later stage of the step waits on a scalar load.
+struct StateIn {
+  Scal S;
+  double T;
+  long long max_steps;
+  bool err;
+};
+
+__device__ inline StateIn read_state(const SolveDesc& sd) {
+  const DevState* st = sd.st;
+  StateIn r;
+  r.S = st->S[sd.par];
+  r.T = st->T;
+  r.max_steps = st->max_steps;
+  r.err = st->err_word != ~0ull;
+  return r;
+}
+
+// This lane's first two partials of the previous launch (lanes: the
+// workgroup size), loaded without a loop so that the loads issue together
+// with the cell loads. Lanes past the end re-read the last partial, which
+// leaves the max unchanged.
 template <bool TWO = true>
-__device__ inline Step begin_step(const SolveDesc& sd, double* red) {
+__device__ inline void load_partials(const SolveDesc& sd, int lanes, double& a, double& b) {
+  const double* pl = sd.part + (long long)sd.par * 2 * sd.nblocks;
+  const int last = sd.nblocks - 1;
+  const int i0 = min((int)threadIdx.x, last), i1 = min((int)threadIdx.x + lanes, last);
+  a = fmax(pl[i0], pl[i1]);
+  b = TWO ? fmax(pl[sd.nblocks + i0], pl[sd.nblocks + i1]) : 0.0;
+}
+
+// Reduce the partials of the previous launch (a, b: this lane's first two,
+// from load_partials) and derive the step scalars from the state read at
+// entry. `red` is this reduction's own LDS scratch (2 * blockDim/64 doubles).
+// With TWO = false the fast-speed partials (all 0) are not read.
+template <bool TWO = true>
+__device__ inline Step begin_step(const SolveDesc& sd, double* red, int lanes, const StateIn& in, double a,
+                                  double b) {
   const double* pl = sd.part + (long long)sd.par * 2 * sd.nblocks;
   const double* pc = pl + sd.nblocks;
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < sd.nblocks; i += blockDim.x) {
+  for (int i = threadIdx.x + 2 * lanes; i < sd.nblocks; i += lanes) {
     a = fmax(a, pl[i]);
     if (TWO) b = fmax(b, pc[i]);
   }
-  block_max2_all<TWO>(a, b, red);
-  const DevState* st = sd.st;
-  return derive_step(st->S[sd.par], st->T, st->max_steps, st->err_word != ~0ull, a, b, sd.ph.ch_factor, sd.xi_mode,
-                     sd.nu, sd.xi_fixed, sd.dx);
+  block_max2_all<TWO>(a, b, red, lanes);
+  return derive_step(in.S, in.T, in.max_steps, in.err, a, b, sd.ph.ch_factor, sd.xi_mode, sd.nu, sd.xi_fixed, sd.dx);
 }
+
+// The same for kernels off the per-step path, which read the state themselves.
+template <bool TWO = true>
+__device__ inline Step begin_step(const SolveDesc& sd, double* red) {
+  const StateIn in = read_state(sd);
+  double a, b;
+  load_partials<TWO>(sd, blockDim.x, a, b);
+  return begin_step<TWO>(sd, red, blockDim.x, in, a, b);
+}
+
+// Population buffer of step n: fa for even n, fb for odd. While a solve
+// advances, launch parity and step parity alternate together, so the buffer
+// a launch reads is predicted as (par ^ npar) and its loads need not wait for
+// n; a launch that finds n of the other parity (a solve resumed after a
+// pause) loads again from the buffer of n.
+__device__ inline int predicted_parity(const SolveDesc& sd) { return (sd.par ^ sd.npar) & 1; }
 
 // End of a step: store this workgroup's maxima for the next launch; workgroup 0
 // advances (t, n) for it, or carries a finished state over unchanged.
@@ -216,7 +266,7 @@ __device__ inline void end_step(const SolveDesc& sd, const Step& S, int tile, do
     pl[sd.nblocks + tile] = cfm;
     if (tile == 0) {
       Scal nx;
-      nx.t = S.landing ? sd.st->T : S.t + sd.dx / S.xi;
+      nx.t = S.landing ? S.T : S.t + sd.dx / S.xi;
       nx.n = S.n + 1;
       nx.done = 0;
       nx.pad = 0;
@@ -402,9 +452,9 @@ struct Kern {
 // halo cell on each side whose collision they recompute.
 // ---------------------------------------------------------------------------
 // 1D step: workgroups of B lanes own B - 2 consecutive output cells plus one
-// halo cell on each side whose collision they recompute. The cell's stored
-// values are loaded before the partials of the previous launch are reduced,
-// so the two memory latencies overlap.
+// halo cell on each side whose collision they recompute. The solve state, the
+// previous launch's partials and the cell's stored values are all loaded at
+// entry (the cell from the predicted buffer), so no load waits on another.
 template <int KIND, class T, int BASIS, int B>
 __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
   using K = Kern<KIND, 1, T, BASIS>;
@@ -415,16 +465,23 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
   const int tid = threadIdx.x;
   const int x = tile * TW - 1 + tid;
   const int xl = map_index(x < N + 1 ? x : N, N, sd.bcx);
-  const long long n0 = sd.st->S[sd.par].n;
+  const StateIn in = read_state(sd);
+  const int bp = predicted_parity(sd);
   T f[Q][P], lo[P];
-  K::load((const T*)((n0 & 1) ? sd.fb : sd.fa), xl, f);
-  K::load_lo((const T*)((n0 & 1) ? sd.fb : sd.fa), xl, lo);
-  const Step S = begin_step<KIND == K_MHD>(sd, red);
+  K::load((const T*)(bp ? sd.fb : sd.fa), xl, f);
+  K::load_lo((const T*)(bp ? sd.fb : sd.fa), xl, lo);
+  double pa, pb;
+  load_partials<KIND == K_MHD>(sd, B, pa, pb);
+  const Step S = begin_step<KIND == K_MHD>(sd, red, B, in, pa, pb);
   if (S.done) {
     carry_done(sd, S, tile);
     return;
   }
   const long long n = S.n;
+  if (int(n & 1) != bp) {
+    K::load((const T*)((n & 1) ? sd.fb : sd.fa), xl, f);
+    K::load_lo((const T*)((n & 1) ? sd.fb : sd.fa), xl, lo);
+  }
   T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
   const double ixi = 1.0 / S.xi, Lam = S.lam, ch = S.ch;
 
@@ -458,7 +515,7 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
     // characteristic boundaries: the boundary cells are replaced afterwards
     if (!(sd.bcx == 2 && (x == 0 || x == N - 1))) K::new_state(sd, Un, x, n + 1, lam, cfm);
   }
-  block_max2<KIND == K_MHD>(lam, cfm, red_end);
+  block_max2<KIND == K_MHD>(lam, cfm, red_end, B);
   end_step(sd, S, tile, lam, cfm);
 }
 
@@ -498,7 +555,7 @@ __global__ void __launch_bounds__(B) k_run1d_wg(const SolveDesc sd, int count) {
       lam = fmax(lam, pl[i]);
       if (MHD) cfm = fmax(cfm, pl[sd.nblocks + i]);
     }
-    block_max2_all<MHD>(lam, cfm, red);
+    block_max2_all<MHD>(lam, cfm, red, B);
   }
   T f[R][Q][P], lo[R][P];
   {
@@ -607,7 +664,7 @@ __global__ void __launch_bounds__(B) k_run1d_wg(const SolveDesc sd, int count) {
     // the barriers inside keep the LDS arrays and `red` from being rewritten
     // by the next step while a lane still reads them
     err = __syncthreads_or(bad) != 0 || err;
-    block_max2_all<MHD>(lm, cm, red);
+    block_max2_all<MHD>(lm, cm, red, B);
     lam = lm;
     cfm = cm;
     t = S.landing ? st->T : S.t + sd.dx / S.xi;
@@ -732,8 +789,9 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   const int tid = threadIdx.x;
   const int x = x0 + tid;
   const int xl = map_index(x < nx + 1 ? x : nx, nx, sd.bcx);
-  const long long n0 = sd.st->S[sd.par].n;
-  const T* __restrict__ src = (const T*)((n0 & 1) ? sd.fb : sd.fa);
+  const StateIn in = read_state(sd);
+  const int bp = predicted_parity(sd);
+  const T* __restrict__ src = (const T*)(bp ? sd.fb : sd.fa);
   // Systems with few values per cell (SW, Euler) load row r + 1 while row r
   // is collided, so a row's memory latency overlaps the previous row's work;
   // MHD has no registers to spare for it.
@@ -746,16 +804,25 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   const long long above = (long long)map_index(y1, ny, sd.bcy) * nx + xl;
   // stored values of row y0 - 1 (only its +y population is used) and of row y0
   T fbelow[Q][P], fraw[Q][P], lo[P], fnext[Q][P], lonext[P];
-  if (PARTIAL) K::load_one(src, below, 3, fbelow[REST], fbelow[3]);
-  else K::load(src, below, fbelow);
-  K::load(src, y0 * nx + xl, fraw);
-  K::load_lo(src, y0 * nx + xl, lo);
-  const Step S = begin_step<KIND == K_MHD>(sd, red);
+  auto load_first = [&]() {
+    if (PARTIAL) K::load_one(src, below, 3, fbelow[REST], fbelow[3]);
+    else K::load(src, below, fbelow);
+    K::load(src, y0 * nx + xl, fraw);
+    K::load_lo(src, y0 * nx + xl, lo);
+  };
+  load_first();
+  double pa, pb;
+  load_partials<KIND == K_MHD>(sd, W, pa, pb);
+  const Step S = begin_step<KIND == K_MHD>(sd, red, W, in, pa, pb);
   if (S.done) {
     carry_done(sd, S, tile);
     return;
   }
   const long long n = S.n;
+  if (int(n & 1) != bp) {
+    src = (const T*)((n & 1) ? sd.fb : sd.fa);
+    load_first();
+  }
   T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
   const double ixi = 1.0 / S.xi, Lam = S.lam, ch = S.ch;
 
@@ -888,7 +955,7 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   if (PARTIAL) K::template relax_one<1>(fraw[REST], fraw[4], false, sd.ph, ixi, Lam, ch, fs[4]);
   else K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
   if (x < nx) finish(y1);
-  block_max2<KIND == K_MHD>(lam, cfm, red_end);
+  block_max2<KIND == K_MHD>(lam, cfm, red_end, W);
   end_step(sd, S, tile, lam, cfm);
 }
 
@@ -946,7 +1013,7 @@ __global__ void __launch_bounds__(256) k_init_reduce(const SolveDesc sd) {
     lam = fmax(lam, l);
     cfm = fmax(cfm, f);
   }
-  block_max2(lam, cfm, red);
+  block_max2(lam, cfm, red, blockDim.x);
   if (threadIdx.x == 0) {
     double* pl = sd.part + (long long)sd.par * 2 * sd.nblocks;
     pl[blockIdx.x] = lam;

@@ -205,6 +205,7 @@ vklb_status admit(vklb_pool* p) {
     const int width = r->grid.dim == 1 ? 256 : 128;  // the batched kernels' tile widths
     r->sd = make_desc(p->base + off, r->L, &r->sys, &r->grid, &r->speed, r->omega, r->bc, &r->eq, width, r->band,
                       default_halo(r->sys.kind));
+    r->sd.npar = int(p->round & 1);  // step 0 runs at the parity of the next round
     // initialization into the parity of the next round
     const long long cells = (long long)r->sd.nx * r->sd.ny;
     PCHK(p, hipMemcpyAsync(const_cast<double*>(r->sd.stage), r->U0.data(), r->U0.size() * 8, hipMemcpyHostToDevice,

@@ -155,7 +155,28 @@ vklb_status hip_fail(vklb_solver* s, hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail((s), e_, #call); \
   } while (0)
 
+// The step graph holds copies of the kernel descriptor; it is rebuilt on the
+// next use after the descriptor changes.
+static void drop_graph(vklb_solver* s) {
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  s->gexec = nullptr;
+  s->graph = nullptr;
+}
+
+// Launches of parity 0 run steps of parity npar (the step kernels predict
+// their source buffer from it).
+static vklb_status set_npar(vklb_solver* s, int npar) {
+  if (s->sd.npar == npar) return VKLB_OK;
+  s->sd.npar = npar;
+  if (s->gexec) HIPCHK(s, hipStreamSynchronize(s->stream));  // no replay in flight
+  drop_graph(s);
+  return VKLB_OK;
+}
+
 vklb_status reset_state(vklb_solver* s, double t, long long n, int done) {
+  vklb_status st = set_npar(s, int(n & 1));
+  if (st != VKLB_OK) return st;
   DevState h;
   memset(&h, 0, sizeof h);
   h.S[0].t = t;
@@ -361,7 +382,13 @@ vklb_status vklb_set_end(vklb_solver* s, double T, int64_t max_steps) {
     HIPCHK(s, hipMemcpyAsync(st + offsetof(DevState, max_steps), &s->max_steps, sizeof(long long),
                              hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(st + done_off, &zero, sizeof(int), hipMemcpyHostToDevice, s->stream));
+    // launches that found the solve finished did not step, so the step
+    // parity of the coming launches is read back
+    long long n = 0;
+    const size_t n_off = offsetof(DevState, S) + size_t(s->launches & 1) * sizeof(Scal) + offsetof(Scal, n);
+    HIPCHK(s, hipMemcpyAsync(&n, st + n_off, sizeof(long long), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
+    return set_npar(s, int((n ^ s->launches) & 1));
   }
   return VKLB_OK;
 }
