@@ -785,30 +785,48 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   const int nx = sd.nx, ny = sd.ny, H = sd.band;
   const int nsx = (nx + W - 1) / W;
   const int sx = tile % nsx, sy = tile / nsx;
-  const int x0 = sx * W, y0 = sy * H, y1 = min(y0 + H, ny);
+  const int x0 = sx * W, y0 = sy * H, y1 = min(y0 + H, ny), nr = y1 - y0;
   const int tid = threadIdx.x;
   const int x = x0 + tid;
   const int xl = map_index(x < nx + 1 ? x : nx, nx, sd.bcx);
+  // MHD bands march up (even sy) or down (odd sy) their rows, so two
+  // neighbouring bands reach the row pair they share at the same time, both
+  // at the start or both at the end: one band's read of the other's edge row
+  // then comes from L2. Those reads are a tenth of an 8-row MHD band's; in
+  // the 32-row bands of the other systems they are a fortieth, and there
+  // alternating measured slower, so those bands all march up. Row of march
+  // index i:
+  constexpr bool ALTERNATE = KIND == K_MHD;
+  const bool down = ALTERNATE && (sy & 1) != 0;
+  auto row_of = [&](int i) { return down ? y1 - 1 - i : y0 + i; };
   const StateIn in = read_state(sd);
   const int bp = predicted_parity(sd);
   const T* __restrict__ src = (const T*)(bp ? sd.fb : sd.fa);
-  // Systems with few values per cell (SW, Euler) load row r + 1 while row r
-  // is collided, so a row's memory latency overlaps the previous row's work;
-  // MHD has no registers to spare for it.
+  // Systems with few values per cell (SW, Euler) load the next row while a
+  // row is collided, so a row's memory latency overlaps the previous row's
+  // work; MHD has no registers to spare for it.
   constexpr bool PREFETCH = Q * P <= 20;
-  // In the delta bases the rows y0 - 1 and y1 and the halo columns use one
+  // In the delta bases the rows next to the band and the halo columns use one
   // population each: they load only U and that population and collide it with
   // the split of its axis alone.
   constexpr bool PARTIAL = DELTA;
+  // The row before the band in march order streams one population into its
+  // first row (y0 - 1: +y up; y1: -y down); the row after it, into its last.
   const long long below = (long long)map_index(y0 - 1, ny, sd.bcy) * nx + xl;
   const long long above = (long long)map_index(y1, ny, sd.bcy) * nx + xl;
-  // stored values of row y0 - 1 (only its +y population is used) and of row y0
-  T fbelow[Q][P], fraw[Q][P], lo[P], fnext[Q][P], lonext[P];
+  const long long pre = down ? above : below, post = down ? below : above;
+  const int qpre = down ? 4 : 3, qpost = down ? 3 : 4;
+  // Array slot that receives the row after the band's population (fixed, so
+  // no register array is indexed at run time).
+  constexpr int PS = ALTERNATE ? 3 : 4;
+  // Stored values of the row before the band (its population in slot 3 of
+  // the array whichever it is) and of the first row.
+  T fpre[Q][P], fraw[Q][P], lo[P], fnext[Q][P], lonext[P];
   auto load_first = [&]() {
-    if (PARTIAL) K::load_one(src, below, 3, fbelow[REST], fbelow[3]);
-    else K::load(src, below, fbelow);
-    K::load(src, y0 * nx + xl, fraw);
-    K::load_lo(src, y0 * nx + xl, lo);
+    if (PARTIAL) K::load_one(src, pre, qpre, fpre[REST], fpre[3]);
+    else K::load(src, pre, fpre);
+    K::load(src, row_of(0) * nx + xl, fraw);
+    K::load_lo(src, row_of(0) * nx + xl, lo);
   };
   load_first();
   double pa, pb;
@@ -826,20 +844,21 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
   const double ixi = 1.0 / S.xi, Lam = S.lam, ch = S.ch;
 
-  __shared__ T s_ex[3][2][P][W];      // row slot, (+x, -x), var, lane
+  __shared__ T s_ex[3][2][P][W];      // march slot, (+x, -x), var, lane
   __shared__ T s_halo[3][2][32][P];   // batch buffer, (left +x, right -x), row, var
 
   T fs[Q][P], U[P];
-  // Row y0 - 1: only its +y population is used (streams into row y0).
-  T prev4[P];
+  // The population the row before the band streams into the first row; then
+  // the one of the row two back in march order (+y up, -y down).
+  T prevm[P];
   if (PARTIAL) {
-    K::template relax_one<1>(fbelow[REST], fbelow[3], true, sd.ph, ixi, Lam, ch, prev4);
+    K::template relax_one<1>(fpre[REST], fpre[3], !down, sd.ph, ixi, Lam, ch, prevm);
   } else {
-    K::relax(fbelow, sd.ph, ixi, Lam, ch, fs, U);
+    K::relax(fpre, sd.ph, ixi, Lam, ch, fs, U);
 #pragma unroll
-    for (int v = 0; v < P; ++v) prev4[v] = fs[3][v];
+    for (int v = 0; v < P; ++v) prevm[v] = down ? fs[4][v] : fs[3][v];
   }
-  // Values of row r-1 carried into iteration r.
+  // Values of the previous row (march order) carried into the next iteration.
   T c_rest[P], c4[P], c5[P], c_lo[P];
   double lam = 0.0, cfm = 0.0;
   // The halo columns are collided by wave 0 in batches of hb rows (lanes
@@ -849,22 +868,23 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   // from being overwritten while a slower wave still reads it.
   const int hb = sd.halo;
 
-  // Finish row rr = r - 1: gather the populations streaming into it (+x/-x
-  // from LDS, +y kept from row r - 2, -y of row r in fs[4]), store them and
+  // Finish the row of march index j, collided one iteration before: gather
+  // the populations streaming into it (+x/-x from LDS; +y and -y from the
+  // current row in fs and the row two back in prevm), store them and
   // U^{n+1}, and take the new state's speeds.
-  auto finish = [&](int r) {
-    const int rr = r - 1;
-    const int ps = rr % 3;
-    const int rb = (rr - y0) / hb;
-    const int hbuf = rb % 3, hr = rr - y0 - rb * hb;
+  auto finish = [&](int j) {
+    const int rr = row_of(j);
+    const int ps = (ALTERNATE ? j : rr) % 3;
+    const int rb = j / hb;
+    const int hbuf = rb % 3, hr = j - rb * hb;
     const long long cell = (long long)rr * nx + x;
     T Un[P];
 #pragma unroll
     for (int v = 0; v < P; ++v) {
       const T a1 = tid > 0 ? s_ex[ps][0][v][tid - 1] : s_halo[hbuf][0][hr][v];
       const T a2 = tid < W - 1 ? s_ex[ps][1][v][tid + 1] : s_halo[hbuf][1][hr][v];
-      const T a4 = prev4[v];
-      const T a5 = fs[4][v];
+      const T a4 = down ? fs[3][v] : prevm[v];
+      const T a5 = down ? prevm[v] : fs[4][v];
       __builtin_nontemporal_store(a1, &dst[K::pidx(0 * P + v, cell)]);
       __builtin_nontemporal_store(a2, &dst[K::pidx(1 * P + v, cell)]);
       __builtin_nontemporal_store(a4, &dst[K::pidx(3 * P + v, cell)]);
@@ -882,13 +902,15 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
     K::new_state(sd, Un, cell, n + 1, lam, cfm);
   };
 
-  for (int r = y0; r < y1; ++r) {
-    const int bq = (r - y0) / hb;
-    if (r - y0 == bq * hb && tid < 64) {
+  // One row: r, at march index i.
+  auto row_step = [&](int i, int r) {
+    const int bq = i / hb;
+    if (i == bq * hb && tid < 64) {
       const int buf = bq % 3;
       const int side = tid >> 5;
-      const int row = r + (tid & 31);
-      if ((tid & 31) < hb && row < y1) {
+      const int k = i + (tid & 31);
+      if ((tid & 31) < hb && k < nr) {
+        const int row = row_of(k);
         const int hx = map_index(side == 0 ? x0 - 1 : x0 + W, nx, sd.bcx);
         if (PARTIAL) {
           T hU[P], hq[P], hs[P];
@@ -904,29 +926,29 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
         }
       }
     }
-    // collide row r; row y0 was loaded before the partials reduction
+    // collide row r; the first row was loaded before the partials reduction
     if (PREFETCH) {
-      if (r + 1 < y1) {
-        K::load(src, (r + 1) * nx + xl, fnext);
-        if (K::COMP) K::load_lo(src, (r + 1) * nx + xl, lonext);
+      if (i + 1 < nr) {
+        K::load(src, row_of(i + 1) * nx + xl, fnext);
+        if (K::COMP) K::load_lo(src, row_of(i + 1) * nx + xl, lonext);
       } else if (PARTIAL) {
-        K::load_one(src, above, 4, fnext[REST], fnext[4]);
+        K::load_one(src, post, qpost, fnext[REST], fnext[PS]);
       } else {
-        K::load(src, above, fnext);
+        K::load(src, post, fnext);
       }
-    } else if (r > y0) {
+    } else if (i > 0) {
       K::load(src, r * nx + xl, fraw);
       if (K::COMP) K::load_lo(src, r * nx + xl, lo);
     }
     K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
-    const int slot = r % 3;
+    const int slot = (ALTERNATE ? i : r) % 3;
 #pragma unroll
     for (int v = 0; v < P; ++v) { s_ex[slot][0][v][tid] = fs[0][v]; s_ex[slot][1][v][tid] = fs[1][v]; }
     __syncthreads();
-    if (r > y0 && x < nx) finish(r);
-    if (r > y0) {
+    if (i > 0 && x < nx) finish(i - 1);
+    if (i > 0) {
 #pragma unroll
-      for (int v = 0; v < P; ++v) prev4[v] = c4[v];
+      for (int v = 0; v < P; ++v) prevm[v] = down ? c5[v] : c4[v];
     }
 #pragma unroll
     for (int v = 0; v < P; ++v) {
@@ -945,16 +967,30 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
         for (int v = 0; v < P; ++v) lo[v] = lonext[v];
       }
     }
+  };
+  // (The loop takes the form each system measured fastest with.)
+  if (ALTERNATE) {
+    for (int i = 0; i < nr; ++i) row_step(i, row_of(i));
+  } else {
+    for (int r = y0; r < y1; ++r) row_step(r - y0, r);
   }
-  // The row above the band: only its -y population is used; it finishes row
-  // y1 - 1 (whose LDS values were published before the last barrier).
+  // The row after the band in march order: only the population it streams
+  // into the last row is used; it finishes that row (whose LDS values were
+  // published before the last barrier).
   if (!PREFETCH) {
-    if (PARTIAL) K::load_one(src, above, 4, fraw[REST], fraw[4]);
-    else K::load(src, above, fraw);
+    if (PARTIAL) K::load_one(src, post, qpost, fraw[REST], fraw[PS]);
+    else K::load(src, post, fraw);
   }
-  if (PARTIAL) K::template relax_one<1>(fraw[REST], fraw[4], false, sd.ph, ixi, Lam, ch, fs[4]);
-  else K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
-  if (x < nx) finish(y1);
+  if (PARTIAL) {
+    K::template relax_one<1>(fraw[REST], fraw[PS], down, sd.ph, ixi, Lam, ch, fs[PS]);
+    if (ALTERNATE) {
+#pragma unroll
+      for (int v = 0; v < P; ++v) fs[4][v] = fs[3][v];
+    }
+  } else {
+    K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
+  }
+  if (x < nx) finish(nr - 1);
   block_max2<KIND == K_MHD>(lam, cfm, red_end, W);
   end_step(sd, S, tile, lam, cfm);
 }
