@@ -154,6 +154,23 @@ def test_tile_shapes_give_identical_results(gpu, prec, basis):
         assert np.array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("prec,basis,bc", [("fp32", 0, "periodic"), ("fp64", 0, "periodic"), ("fp32", 3, "periodic"),
+                                           ("fp32", 0, "zero_gradient")])
+def test_mhd_tile_shapes_give_identical_results(gpu, prec, basis, bc):
+    """MHD bands march up and down in turn; every strip width, band height
+    (even and odd band counts, a short last band, one-row bands) and halo
+    batch gives the same bits, with periodic and zero-gradient boundaries."""
+    P = I.orszag_tang(96, steps=20, bc=(bc, bc))
+    outs = []
+    for w, b, h in ((256, 8, 0), (64, 5, 2), (128, 7, 7), (256, 1, 1), (64, 40, 32), (256, 3, 8)):
+        s = gpu.Solver(P, precision=prec, basis=basis, strip_width=w, band_rows=b, halo_rows=h)
+        s.init()
+        outs.append(s.run())
+        s.close()
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and o[1:] == outs[0][1:]
+
+
 @pytest.mark.parametrize("dim", [1, 2])
 def test_centered_preset_equals_its_weighted_parameters(gpu, dim):
     """VKLB_EQ_CENTERED is the weighted set with c = 1/3 (1/5), k = 0 and the
