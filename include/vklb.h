@@ -231,7 +231,7 @@ void vklb_destroy(vklb_solver* s);
  *  - 1D candidates: 256- or 512-lane workgroups; grids of up to 1024 cells
  *    (not MHD) that run in one workgroup: 256, 512 or 1024 lanes.
  *  - 2D candidates: strips of 64/128/256 columns, bands of 4..64 rows, halo
- *    batches of 2, 8 or 16 rows.
+ *    batches of 2, 8, 16 or 32 rows.
  * All shapes give identical results, so the choice only affects speed. The
  * end condition is ignored while timing. Allocates one workspace
  * (vklb_workspace_bytes) for the duration of the call and synchronizes.

@@ -97,8 +97,8 @@ inline int default_width(int dim, long long nx) {
 // compute unit, so it takes short bands to have enough of them.
 inline int default_band(int kind) { return kind == VKLB_MHD_GLM ? 8 : 32; }
 // Rows of halo columns per batch (1..32): measured fastest on MI355X with the
-// default bands (MHD 8 of 8 rows; the others 16 of 32, 2.6% over 2).
-inline int default_halo(int kind) { return kind == VKLB_MHD_GLM ? 8 : 16; }
+// default bands, one batch per band (MHD 8 rows; the others 32, 3% over 2).
+inline int default_halo(int kind) { return kind == VKLB_MHD_GLM ? 8 : 32; }
 
 inline int step_grid_of(const vklb_grid* g, int width, int band) {
   if (g->dim == 1) return int((g->n[0] + width - 3) / (width - 2));

@@ -327,6 +327,19 @@ struct Kern {
       for (int v = 0; v < P; ++v) f[q][v] = src[pidx(q * P + v, cell)];
   }
 
+  // 2D rows of the strip's own cells, which no other workgroup of the launch
+  // reads: non-temporal loads, so those lines leave L2 before the halo-column
+  // and edge-row lines that neighbouring workgroups read again. (1D steps keep
+  // plain loads: their cells stay cache-resident from one launch to the next.)
+  __device__ static inline void load_stream(const T* __restrict__ src, long long cell, T (&f)[Q][P], T (&lo)[P]) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int v = 0; v < P; ++v) f[q][v] = __builtin_nontemporal_load(&src[pidx(q * P + v, cell)]);
+#pragma unroll
+    for (int v = 0; v < P; ++v) lo[v] = COMP ? __builtin_nontemporal_load(&src[pidx(Q * P + v, cell)]) : T(0);
+  }
+
   // Low part of U (compensated basis only).
   __device__ static inline void load_lo(const T* __restrict__ src, long long cell, T (&lo)[P]) {
 #pragma unroll
@@ -825,8 +838,7 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   auto load_first = [&]() {
     if (PARTIAL) K::load_one(src, pre, qpre, fpre[REST], fpre[3]);
     else K::load(src, pre, fpre);
-    K::load(src, row_of(0) * nx + xl, fraw);
-    K::load_lo(src, row_of(0) * nx + xl, lo);
+    K::load_stream(src, row_of(0) * nx + xl, fraw, lo);
   };
   load_first();
   double pa, pb;
@@ -929,16 +941,14 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
     // collide row r; the first row was loaded before the partials reduction
     if (PREFETCH) {
       if (i + 1 < nr) {
-        K::load(src, row_of(i + 1) * nx + xl, fnext);
-        if (K::COMP) K::load_lo(src, row_of(i + 1) * nx + xl, lonext);
+        K::load_stream(src, row_of(i + 1) * nx + xl, fnext, lonext);
       } else if (PARTIAL) {
         K::load_one(src, post, qpost, fnext[REST], fnext[PS]);
       } else {
         K::load(src, post, fnext);
       }
     } else if (i > 0) {
-      K::load(src, r * nx + xl, fraw);
-      if (K::COMP) K::load_lo(src, r * nx + xl, lo);
+      K::load_stream(src, r * nx + xl, fraw, lo);
     }
     K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
     const int slot = (ALTERNATE ? i : r) % 3;

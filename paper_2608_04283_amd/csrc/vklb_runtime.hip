@@ -636,7 +636,7 @@ vklb_status vklb_tune(const vklb_system* sys, vklb_lattice lat, const vklb_grid*
       if (w > 64 && (nx + w - 1) / w * w - nx >= w / 2) continue;  // mostly idle lanes
       for (int band : {4, 8, 16, 32, 64}) {
         if (band > 4 && band / 2 >= ny) continue;
-        for (int halo : {2, 8, 16}) {
+        for (int halo : {2, 8, 16, 32}) {
           if (halo > band) continue;
           vklb_options o = b0;
           o.strip_width = w;
