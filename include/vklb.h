@@ -83,8 +83,8 @@ typedef struct {
  *  periodic (Sec. 3.3);
  *  zero gradient (the ghost beyond a boundary carries the post-collision
  *    populations of the boundary cell);
- *  characteristic, non-reflecting (Sec. 3.3; 1D only, every system;
- *    VKLB_ERR_UNSUPPORTED in 2D and in the serving pool): at a boundary cell
+ *  characteristic, non-reflecting (Sec. 3.3; 1D only, every system, also
+ *    in the serving pool; VKLB_ERR_UNSUPPORTED in 2D): at a boundary cell
  *    the characteristic variables W = P^{-1} U advance with the outgoing
  *    waves only, dW/dx taken as the first-order one-sided difference towards
  *    the interior, U_b^{n+1} = U_b - P (Lambda dW)' / xi, and the cell's

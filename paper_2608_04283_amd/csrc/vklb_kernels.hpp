@@ -461,16 +461,16 @@ struct Kern {
 };
 
 // ---------------------------------------------------------------------------
-// 1D step: workgroups of 256 lanes own 254 consecutive output cells plus one
-// halo cell on each side whose collision they recompute.
-// ---------------------------------------------------------------------------
 // 1D step: workgroups of B lanes own B - 2 consecutive output cells plus one
 // halo cell on each side whose collision they recompute. The solve state, the
 // previous launch's partials and the cell's stored values are all loaded at
 // entry (the cell from the predicted buffer), so no load waits on another.
-template <int KIND, class T, int BASIS, int B>
+// The tiles holding the end cells apply characteristic boundaries in place.
+// ---------------------------------------------------------------------------
+template <int KIND, class T, int BASIS, int B, bool CHARBC>
 __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
   using K = Kern<KIND, 1, T, BASIS>;
+  using ST = typename K::ST;
   constexpr bool DELTA = K::DELTA;
   constexpr int P = K::P, Q = 3, TW = B - 2;
   __shared__ double red[2 * (B / 64) + 2], red_end[2 * (B / 64) + 2];
@@ -499,34 +499,74 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
   const double ixi = 1.0 / S.xi, Lam = S.lam, ch = S.ch;
 
   __shared__ T s_plus[P][B], s_minus[P][B];
+  __shared__ T s_unb[2][P];  // characteristic boundaries: U^n of cells 1 and N - 2
 
   T fs[Q][P], U[P];
   K::relax(f, sd.ph, ixi, Lam, ch, fs, U);
 #pragma unroll
   for (int v = 0; v < P; ++v) { s_plus[v][tid] = fs[0][v]; s_minus[v][tid] = fs[2][v]; }
+  // Characteristic boundaries (CHARBC: compiled in, applied when the solve
+  // uses them). The tile holding a boundary cell also holds its interior
+  // neighbour (as an own or a halo cell), whose U^n the condition needs.
+  const bool charbc = CHARBC && sd.bcx == 2 && N >= 2;
+  if (charbc && (x == 1 || x == N - 2)) {
+#pragma unroll
+    for (int v = 0; v < P; ++v) s_unb[x == 1 ? 0 : 1][v] = U[v];
+  }
   __syncthreads();
 
   double lam = 0.0, cfm = 0.0;
   if (tid >= 1 && tid <= TW && x < N) {
     T Un[P];
+    if (!(charbc && (x == 0 || x == N - 1))) {
 #pragma unroll
-    for (int v = 0; v < P; ++v) {
-      const T a = s_plus[v][tid - 1];
-      const T b = s_minus[v][tid + 1];
-      dst[K::pidx(0 * P + v, x)] = a;
-      dst[K::pidx(2 * P + v, x)] = b;
-      if (DELTA) {
-        T lo_new;
-        Un[v] = K::advance(U[v], (a - fs[0][v]) + (b - fs[2][v]), lo[v], lo_new);
-        dst[K::pidx(1 * P + v, x)] = Un[v];
-        if (K::COMP) dst[K::pidx(Q * P + v, x)] = lo_new;
-      } else {
-        dst[K::pidx(1 * P + v, x)] = fs[1][v];
-        Un[v] = ((T(0) + a) + fs[1][v]) + b;
+      for (int v = 0; v < P; ++v) {
+        const T a = s_plus[v][tid - 1];
+        const T b = s_minus[v][tid + 1];
+        dst[K::pidx(0 * P + v, x)] = a;
+        dst[K::pidx(2 * P + v, x)] = b;
+        if (DELTA) {
+          T lo_new;
+          Un[v] = K::advance(U[v], (a - fs[0][v]) + (b - fs[2][v]), lo[v], lo_new);
+          dst[K::pidx(1 * P + v, x)] = Un[v];
+          if (K::COMP) dst[K::pidx(Q * P + v, x)] = lo_new;
+        } else {
+          dst[K::pidx(1 * P + v, x)] = fs[1][v];
+          Un[v] = ((T(0) + a) + fs[1][v]) + b;
+        }
+      }
+    } else {
+      // Characteristic (non-reflecting) boundary of Sec. 3.3: from U^n of the
+      // boundary cell b and of its interior neighbour, the characteristic
+      // variables advance with the outgoing waves only (first-order one-sided
+      // difference, linearized about b), U_b^{n+1} = U_b - P (Lambda dW)' / xi,
+      // and b's populations become f^eq(U_b^{n+1}) with this step's xi and
+      // Lambda (the compensated low part 0); its speeds join the tile's maxima.
+      const int side = x == 0 ? 0 : 1;
+      ST us[P], du[P], corr[P], unew[P];
+#pragma unroll
+      for (int v = 0; v < P; ++v) {
+        us[v] = ST(U[v]);
+        const ST nb = ST(s_unb[side][v]);
+        du[v] = side == 1 ? ST(U[v]) - nb : nb - ST(U[v]);
+      }
+      Cell<KIND, 1, ST>::char_correction(us, du, sd.ph, ST(ch), side == 1, corr);
+#pragma unroll
+      for (int v = 0; v < P; ++v) unew[v] = us[v] - corr[v] * ST(ixi);
+      ST fe[Q][P];
+      Equilibrium<KIND, 1, ST>::eval(unew, sd.ph, ST(ixi), ST(Lam), ST(ch), fe);
+#pragma unroll
+      for (int v = 0; v < P; ++v) Un[v] = T(unew[v]);
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int v = 0; v < P; ++v) dst[K::pidx(q * P + v, x)] = (DELTA && q == K::REST) ? Un[v] : T(fe[q][v]);
+      if (K::COMP) {
+#pragma unroll
+        for (int v = 0; v < P; ++v) dst[K::pidx(Q * P + v, x)] = T(0);
       }
     }
-    // characteristic boundaries: the boundary cells are replaced afterwards
-    if (!(sd.bcx == 2 && (x == 0 || x == N - 1))) K::new_state(sd, Un, x, n + 1, lam, cfm);
+    K::new_state(sd, Un, x, n + 1, lam, cfm);
   }
   block_max2<KIND == K_MHD>(lam, cfm, red_end, B);
   end_step(sd, S, tile, lam, cfm);
@@ -644,8 +684,8 @@ __global__ void __launch_bounds__(B) k_run1d_wg(const SolveDesc sd, int count) {
           f[r][2][v] = b;
         }
         if (charbc && (c == 0 || c == N - 1)) {
-          // characteristic boundary (Sec. 3.3), as k_char_bc1d does it after a
-          // step launch: from U^n of the cell and of its interior neighbour,
+          // characteristic boundary (Sec. 3.3), as step1d_tile does it: from
+          // U^n of the cell and of its interior neighbour,
           // U_b^{n+1} = U_b - P (Lambda dW)' / xi, populations f^eq(U_b^{n+1})
           const int side = c == 0 ? 0 : 1;
           ST us[P], du[P], corr[P], unew[P];
@@ -714,67 +754,10 @@ __global__ void __launch_bounds__(B) k_run1d_wg(const SolveDesc sd, int count) {
   }
 }
 
-// Characteristic (non-reflecting) boundaries of Sec. 3.3, 1D, launched after
-// the step kernel of the same parity. From U^n of the boundary cell b and of
-// its interior neighbour (the step's source buffer): the characteristic
-// variables advance with the outgoing waves only (first-order one-sided
-// difference, linearized about b), U_b^{n+1} = U_b - P (Lambda dW)' / xi,
-// and b's populations in the new buffer become f^eq(U_b^{n+1}) with this
-// step's xi and Lambda. The step kernel left b out of its maxima; this kernel
-// folds U_b^{n+1}'s speeds into the partials of b's tile (0 or the last).
-template <int KIND, class T, int BASIS>
-__global__ void __launch_bounds__(64) k_char_bc1d(const SolveDesc sd) {
-  using K = Kern<KIND, 1, T, BASIS>;
-  using ST = typename K::ST;
-  constexpr int P = K::P, Q = 3;
-  __shared__ double red[4];
-  const Step S = begin_step(sd, red);  // every lane: the wave reductions need all 64
-  if (S.done || threadIdx.x != 0) return;
-  const int N = sd.nx;
-  if (N < 2) return;
-  const long long n = S.n;
-  const T* __restrict__ src = (const T*)((n & 1) ? sd.fb : sd.fa);
-  T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
-  const double ixi = 1.0 / S.xi;
-  double* pl = sd.part + (long long)(sd.par ^ 1) * 2 * sd.nblocks;
-  for (int side = 0; side < 2; ++side) {
-    const int b = side == 0 ? 0 : N - 1, nb = side == 0 ? 1 : N - 2;
-    T Ub[P], Unb[P];
-    K::moments_of(src, b, Ub);
-    K::moments_of(src, nb, Unb);
-    ST us[P], du[P], corr[P], unew[P];
-#pragma unroll
-    for (int v = 0; v < P; ++v) {
-      us[v] = ST(Ub[v]);
-      du[v] = side == 1 ? ST(Ub[v]) - ST(Unb[v]) : ST(Unb[v]) - ST(Ub[v]);
-    }
-    Cell<KIND, 1, ST>::char_correction(us, du, sd.ph, ST(S.ch), side == 1, corr);
-#pragma unroll
-    for (int v = 0; v < P; ++v) unew[v] = us[v] - corr[v] * ST(ixi);
-    ST fe[Q][P];
-    Equilibrium<KIND, 1, ST>::eval(unew, sd.ph, ST(ixi), ST(S.lam), ST(S.ch), fe);
-    T Ut[P];
-#pragma unroll
-    for (int v = 0; v < P; ++v) Ut[v] = T(unew[v]);
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-#pragma unroll
-      for (int v = 0; v < P; ++v) dst[K::pidx(q * P + v, b)] = (K::DELTA && q == K::REST) ? Ut[v] : T(fe[q][v]);
-    if (K::COMP) {
-#pragma unroll
-      for (int v = 0; v < P; ++v) dst[K::pidx(Q * P + v, b)] = T(0);
-    }
-    double lam = 0.0, cfm = 0.0;
-    K::new_state(sd, Ut, b, n + 1, lam, cfm);  // non-finite or non-physical: flagged here
-    const int tile = side == 0 ? 0 : sd.nblocks - 1;
-    pl[tile] = fmax(pl[tile], lam);
-    pl[sd.nblocks + tile] = fmax(pl[sd.nblocks + tile], cfm);
-  }
-}
 
-template <int KIND, class T, int BASIS, int B>
+template <int KIND, class T, int BASIS, int B, bool CHARBC>
 __global__ void __launch_bounds__(B) k_step1d(const SolveDesc sd) {
-  step1d_tile<KIND, T, BASIS, B>(sd, blockIdx.x);
+  step1d_tile<KIND, T, BASIS, B, CHARBC>(sd, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1030,7 +1013,7 @@ __global__ void __launch_bounds__(W) k_step_batched(const SolveDesc* __restrict_
   const WorkItem w = work[i];
   SolveDesc sd = descs[w.slot];
   sd.par = par;
-  if constexpr (DIM == 1) step1d_tile<KIND, T, BASIS, 256>(sd, w.tile);
+  if constexpr (DIM == 1) step1d_tile<KIND, T, BASIS, 256, true>(sd, w.tile);
   else step2d_tile<KIND, T, BASIS, W>(sd, w.tile);
 }
 

@@ -18,7 +18,6 @@ struct Launchers {
   launch_fn step = nullptr;
   launch_fn moments = nullptr;
   batched_fn batched = nullptr;  // serving: tiles of many solves in one launch
-  launch_fn char_bc = nullptr;   // 1D characteristic boundaries
   wg_fn run_wg = nullptr;        // 1D grids of up to wg_max_cells: many steps in one workgroup
   int wg_max_cells = 0;
   int block = 256;  // threads per step workgroup

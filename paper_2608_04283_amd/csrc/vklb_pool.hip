@@ -322,8 +322,6 @@ vklb_status vklb_pool_submit(vklb_pool* p, const vklb_request* rq, uint64_t* tic
   vklb_status st = validate(&rq->sys, rq->lat, &rq->grid, &rq->lambda, rq->omega, rq->bc, &rq->eq, p->prec, &msg);
   if (st != VKLB_OK) return pfail(p, st, msg);
   if (!isfinite(rq->T) && rq->max_steps < 0) return pfail(p, VKLB_ERR_ARG, "a request needs an end time or a step limit");
-  if (rq->bc[0] == VKLB_BC_CHARACTERISTIC || (rq->grid.dim == 2 && rq->bc[1] == VKLB_BC_CHARACTERISTIC))
-    return pfail(p, VKLB_ERR_UNSUPPORTED, "characteristic boundaries are not served by the pool");
   Req* r = new Req();
   r->ticket = p->next_ticket++;
   r->tag = rq->tag;

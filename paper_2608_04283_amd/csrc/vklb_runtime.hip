@@ -193,11 +193,9 @@ vklb_status reset_state(vklb_solver* s, double t, long long n, int done) {
 
 vklb_status launch_steps(vklb_solver* s, hipStream_t st, long long n, long long first_launch) {
   SolveDesc d = s->sd;
-  const bool charbc = d.bcx == 2;
   for (long long i = 0; i < n; ++i) {
     d.par = int((first_launch + i) & 1);
     HIPCHK(s, s->K.step(d, s->step_grid, st));
-    if (charbc) HIPCHK(s, s->K.char_bc(d, 1, st));
   }
   return VKLB_OK;
 }

@@ -51,6 +51,33 @@ def test_alone_equals_mix_bitwise(gpu):
         assert np.array_equal(c["U"], U), rq.problem.name
 
 
+def test_characteristic_boundaries_served_bitwise(gpu):
+    """1D solves with characteristic boundaries (every system, grids in one
+    workgroup and above) give the same bits served by the pool, next to
+    periodic ones, as alone."""
+    reqs = []
+    for rid, (system, n, steps) in enumerate((("sw", 700, 60), ("euler", 1500, 90), ("mhd", 200, 40),
+                                              ("mhd", 2100, 50), ("euler", 600, 30), ("sw", 3000, 70))):
+        P = I.random_riemann(system, 1, n, seed=900 + rid, max_steps=steps)
+        if rid != 4:
+            P = P.with_(bc=("characteristic", "characteristic"))
+        reqs.append(I.Request(rid=rid, arrival=0.0, problem=P, steps=steps))
+    pool = gpu.Pool(1 << 30, "fp32")
+    for rq in reqs:
+        pool.submit(rq.problem, tag=rq.rid)
+    got = {}
+    while len(got) < len(reqs):
+        pool.run(8)
+        for c in pool.poll():
+            got[c["tag"]] = c
+    pool.close()
+    for rq in reqs:
+        c = got[rq.rid]
+        U, t, n = alone(gpu, rq.problem)
+        assert c["status"] == 0 and c["steps"] == n == rq.steps and c["t"] == t
+        assert np.array_equal(c["U"], U), rq.problem.name
+
+
 def test_admission_under_small_budget(gpu):
     reqs = small_mix(9, seed=5)
     sizes = [gpu.workspace_bytes(r.problem, "fp32") for r in reqs]
