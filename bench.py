@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
     # name: (problem factory, precisions, cpu-baseline sample steps)
-    "euler1d_sod": (lambda: I.sod(65536), ("fp32", "fp64"), 1500),
+    "euler1d_sod": (lambda: I.sod(65536), ("fp32", "fp64"), 3500),
     "sw1d_dambreak": (lambda: I.dam_break(1000, c=0.5, k=0.0), ("fp64",), 600),
     "euler2d_quadrants": (lambda: I.quadrants(2048, seed=0, steps=2000), ("fp32",), 4),
     "mhd1d_briowu": (lambda: I.brio_wu(16384), ("fp32",), 300),
