@@ -227,7 +227,9 @@ def main():
     prec = args.precision or precs[0]
     main_res = time_workload(args.workload, prec, args.steps, args.warmup)
     out = {
-        "metric": "Mcell-steps/s",
+        # the headline metric; its HBM fraction is roofline.frac, FP64 is under
+        # other_precision, served solves/s and p50/p99 latency under serving
+        "metric": "Mcell-steps/s & % HBM roofline, FP32 vs FP64; served solves/s, p50/p99 latency",
         "value": round(main_res["value"], 2),
         "unit": "Mcell-steps/s",
         "n_gpus": 1,
