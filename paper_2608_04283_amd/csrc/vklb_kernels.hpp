@@ -508,10 +508,16 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
   // Characteristic boundaries (CHARBC: compiled in, applied when the solve
   // uses them). The tile holding a boundary cell also holds its interior
   // neighbour (as an own or a halo cell), whose U^n the condition needs.
+  // With N = 3 the middle cell is the neighbour of both boundaries, so one
+  // lane fills both slots.
   const bool charbc = CHARBC && sd.bcx == 2 && N >= 2;
-  if (charbc && (x == 1 || x == N - 2)) {
+  if (charbc && x == 1) {
 #pragma unroll
-    for (int v = 0; v < P; ++v) s_unb[x == 1 ? 0 : 1][v] = U[v];
+    for (int v = 0; v < P; ++v) s_unb[0][v] = U[v];
+  }
+  if (charbc && x == N - 2) {
+#pragma unroll
+    for (int v = 0; v < P; ++v) s_unb[1][v] = U[v];
   }
   __syncthreads();
 

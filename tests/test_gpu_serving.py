@@ -53,11 +53,13 @@ def test_alone_equals_mix_bitwise(gpu):
 
 def test_characteristic_boundaries_served_bitwise(gpu):
     """1D solves with characteristic boundaries (every system, grids in one
-    workgroup and above) give the same bits served by the pool, next to
-    periodic ones, as alone."""
+    workgroup and above, and the three- and two-cell grids whose middle or
+    other cell is the neighbour of both boundaries) give the same bits served
+    by the pool, next to periodic ones, as alone."""
     reqs = []
     for rid, (system, n, steps) in enumerate((("sw", 700, 60), ("euler", 1500, 90), ("mhd", 200, 40),
-                                              ("mhd", 2100, 50), ("euler", 600, 30), ("sw", 3000, 70))):
+                                              ("mhd", 2100, 50), ("euler", 600, 30), ("sw", 3000, 70),
+                                              ("euler", 3, 25), ("mhd", 3, 25), ("sw", 2, 25))):
         P = I.random_riemann(system, 1, n, seed=900 + rid, max_steps=steps)
         if rid != 4:
             P = P.with_(bc=("characteristic", "characteristic"))
