@@ -6,7 +6,8 @@ workgroup tile (254 cells), of the one-workgroup limit (1024 cells, MHD 256),
 of a 2D strip (256 columns, 64 and 128 for narrow grids) and of a band (32
 rows, MHD 8), on both boundary rules, both precisions and both 1D paths (one
 workgroup for small grids, one launch per step). Characteristic boundaries
-take their smallest grid, two cells. Tolerances as in the other parity tests:
+take their smallest grids: two cells, and three, whose middle cell is the
+neighbour of both boundaries. Tolerances as in the other parity tests:
 relative L1 per field <= 1e-12 (FP64) and <= 1e-4 (FP32).
 """
 import numpy as np
@@ -113,3 +114,23 @@ def test_2d_strip_and_band_edges(gpu, oracle, system, shape, prec):
     mixed boundary rules (periodic in x, zero gradient in y)."""
     P = two_state_2d(system, shape[0], shape[1], 51, max_steps=20, bc=("periodic", "zero_gradient"))
     check(gpu, oracle, P, prec)
+
+
+EDGE_PROBLEMS = {
+    "euler1d_n1_periodic": (lambda: I.random_riemann("euler", 1, 1, 61, max_steps=20, bc=("periodic", "periodic")), {}),
+    "euler1d_n3_characteristic": (lambda: I.random_riemann("euler", 1, 3, 62, max_steps=20,
+                                                           bc=("characteristic", "characteristic")), {"small_grid": -1}),
+    "mhd1d_n2_zero_gradient": (lambda: I.random_riemann("mhd", 1, 2, 63, max_steps=20), {"small_grid": -1}),
+    "mhd2d_1x1_zero_gradient": (lambda: two_state_2d("mhd", 1, 1, 64, max_steps=10), {}),
+    "euler2d_2x3_periodic": (lambda: two_state_2d("euler", 2, 3, 65, max_steps=10, bc=("periodic", "periodic")), {}),
+    "sw2d_257x33_mixed": (lambda: two_state_2d("sw", 257, 33, 66, max_steps=15, bc=("periodic", "zero_gradient")), {}),
+}
+
+
+@pytest.mark.parametrize("prec,basis", [("fp64", 1), ("fp64", 2), ("fp32", 1), ("fp32", 2), ("fp32", 3)])
+@pytest.mark.parametrize("name", list(EDGE_PROBLEMS))
+def test_edge_grids_every_basis(gpu, oracle, name, prec, basis):
+    """The stored bases (populations, delta, compensated) at edge sizes: the
+    delta bases collide halo cells and band edge rows with one population."""
+    factory, opts = EDGE_PROBLEMS[name]
+    check(gpu, oracle, factory(), prec, basis=basis, **opts)
