@@ -134,3 +134,38 @@ def test_edge_grids_every_basis(gpu, oracle, name, prec, basis):
     delta bases collide halo cells and band edge rows with one population."""
     factory, opts = EDGE_PROBLEMS[name]
     check(gpu, oracle, factory(), prec, basis=basis, **opts)
+
+
+def test_tiny_grids_served(gpu, oracle):
+    """Grids of one to a few cells in the serving pool, every system, both
+    dimensions and boundary rules: the same bits as alone, and the oracle's
+    result to the FP32 tolerance."""
+    probs = []
+    for k, system in enumerate(("sw", "euler", "mhd")):
+        for n in (1, 2, 5):
+            bc = ("periodic", "periodic") if n != 2 else ("zero_gradient", "zero_gradient")
+            probs.append(I.random_riemann(system, 1, n, 70 + 3 * k + n, max_steps=15 + n, bc=bc))
+        for shape in ((1, 1), (1, 5), (5, 1), (2, 3)):
+            bc = ("zero_gradient", "periodic") if shape[0] > shape[1] else ("periodic", "zero_gradient")
+            probs.append(two_state_2d(system, shape[0], shape[1], 80 + k, max_steps=9 + shape[1], bc=bc))
+    pool = gpu.Pool(1 << 28, "fp32")
+    for i, P in enumerate(probs):
+        pool.submit(P, tag=i)
+    got = {}
+    while len(got) < len(probs):
+        pool.run(8)
+        for c in pool.poll():
+            got[c["tag"]] = c
+    pool.close()
+    for i, P in enumerate(probs):
+        print(f"[served] {P.name} n={P.n} bc={P.bc}", flush=True)
+        c = got[i]
+        s = gpu.Solver(P, precision="fp32")
+        s.init()
+        U, t, n = s.run()
+        s.close()
+        assert c["status"] == 0 and c["steps"] == n == P.max_steps and c["t"] == t
+        assert np.array_equal(c["U"], U), P.name
+        ref = run_oracle(oracle, P)
+        assert ref["status"] == 0 and ref["steps"] == n
+        assert np.all(rel_l1(U, ref["U"]) <= TOL["fp32"]), P.name
