@@ -142,6 +142,11 @@ typedef struct {
                        run up to 1024 steps per launch in one workgroup, with bitwise the same
                        results as one launch per step: 0 = on, 512 lanes (256 for MHD), the fastest
                        measured; 256, 512 or 1024 = on with that many lanes; -1 = off */
+  int fold_partials; /* the per-workgroup maxima a step leaves for the next (max |lambda|, max
+                       c_f) are read by every workgroup of the next launch; for a step grid of
+                       more than this many workgroups a one-workgroup kernel after each launch
+                       folds them into one value instead, which the next launch reads. Results
+                       are bitwise the same. 0 = 2048; -1 = never */
 } vklb_options;
 
 typedef struct vklb_solver vklb_solver;

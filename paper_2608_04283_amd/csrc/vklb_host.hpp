@@ -51,6 +51,9 @@ inline int resolve_basis(int opt, vklb_precision prec, int dim) {
 }
 
 constexpr int kDiagBlocks = 512;
+// Step grids of more workgroups than this fold each launch's partials into
+// one entry (vklb_options.fold_partials = 0).
+constexpr int kFoldAbove = 2048;
 
 // Upper bound of the step grid over every strip width / band height choice.
 inline long long max_step_blocks(const vklb_grid* g) {
@@ -196,6 +199,7 @@ inline SolveDesc make_desc(char* base, const Layout& L, const vklb_system* sys, 
   d.band = band;
   d.halo = halo;
   d.nblocks = step_grid_of(grid, width, band);
+  d.nred = d.nblocks;
   return d;
 }
 

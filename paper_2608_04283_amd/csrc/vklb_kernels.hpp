@@ -17,6 +17,9 @@
 // c_f) with plain stores into a partials array. The kernel boundary is the
 // global synchronization: every workgroup of the next launch reduces all the
 // partials itself and derives the same xi, Lambda, c_h and end condition.
+// That costs every workgroup one load per workgroup of the grid; above a few
+// thousand workgroups the runtime instead folds each launch's partials into
+// one entry with a one-workgroup kernel, and the next launch reads that.
 // Scalars (t, n) and partials are double buffered by launch parity, so the
 // step needs no fence, no atomic and no "last workgroup" election.
 #pragma once
@@ -69,6 +72,8 @@ struct SolveDesc {
   int par;               // launch parity
   int halo;              // 2D rows of halo columns collided per batch (1..32)
   int npar;              // parity of the step index at launches of parity 0
+  int nred;              // partials a step launch reduces at entry: nblocks, or 1 when
+                         // each launch's partials are folded into entry 0 after it
 };
 
 // Values every workgroup derives at the start of a step.
@@ -217,22 +222,22 @@ __device__ inline StateIn read_state(const SolveDesc& sd) {
 template <bool TWO = true>
 __device__ inline void load_partials(const SolveDesc& sd, int lanes, double& a, double& b) {
   const double* pl = sd.part + (long long)sd.par * 2 * sd.nblocks;
-  const int last = sd.nblocks - 1;
+  const int last = sd.nred - 1;
   const int i0 = min((int)threadIdx.x, last), i1 = min((int)threadIdx.x + lanes, last);
   a = fmax(pl[i0], pl[i1]);
   b = TWO ? fmax(pl[sd.nblocks + i0], pl[sd.nblocks + i1]) : 0.0;
 }
 
 // Reduce the partials of the previous launch (a, b: this lane's first two,
-// from load_partials) and derive the step scalars from the state read at
-// entry. `red` is this reduction's own LDS scratch (2 * blockDim/64 doubles).
+// from load_partials; the first nred of them) and derive the step scalars
+// from the state read at entry. `red` is this reduction's own LDS scratch (2 * blockDim/64 doubles).
 // With TWO = false the fast-speed partials (all 0) are not read.
 template <bool TWO = true>
 __device__ inline Step begin_step(const SolveDesc& sd, double* red, int lanes, const StateIn& in, double a,
                                   double b) {
   const double* pl = sd.part + (long long)sd.par * 2 * sd.nblocks;
   const double* pc = pl + sd.nblocks;
-  for (int i = threadIdx.x + 2 * lanes; i < sd.nblocks; i += lanes) {
+  for (int i = threadIdx.x + 2 * lanes; i < sd.nred; i += lanes) {
     a = fmax(a, pl[i]);
     if (TWO) b = fmax(b, pc[i]);
   }

@@ -66,6 +66,38 @@ __global__ void k_totals_final(const double* __restrict__ part, int nblk, int p,
   out[v] = S + C;
 }
 
+// One workgroup folds the per-workgroup maxima of parity `par` into entry 0
+// of each half (max |lambda|, max c_f). The max is exact and independent of
+// order, so a launch that reads entry 0 alone derives the step every
+// workgroup would derive from all the entries. Eight loads per lane and
+// iteration keep enough of them in flight for a million workgroups.
+__global__ void __launch_bounds__(1024) k_fold_partials(const SolveDesc sd, int par) {
+  __shared__ double red[2 * 16 + 2];
+  double* pl = sd.part + (long long)par * 2 * sd.nblocks;
+  const double* pc = pl + sd.nblocks;
+  const int nb = sd.nblocks;
+  double a = 0.0, b = 0.0;
+  for (int i0 = threadIdx.x; i0 < nb; i0 += 8 * 1024) {
+    double x[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * 1024;
+      x[u] = i < nb ? pl[i] : 0.0;
+      y[u] = i < nb ? pc[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a = fmax(a, x[u]);
+      b = fmax(b, y[u]);
+    }
+  }
+  block_max2_all<true>(a, b, red, 1024);
+  if (threadIdx.x == 0) {
+    pl[0] = a;
+    pl[nb] = b;
+  }
+}
+
 // max |dBx/dx + dBy/dy| by central differences on the FP64 moments; ghosts
 // follow the boundary rule (periodic wrap or copy of the boundary cell).
 __global__ void k_divb(const double* __restrict__ U, int nx, int ny, double dx, int bcx, int bcy,
@@ -191,11 +223,22 @@ vklb_status reset_state(vklb_solver* s, double t, long long n, int done) {
   return VKLB_OK;
 }
 
+// Folds the partials of parity `par` into entry 0 when the solve's step
+// launches read that entry alone.
+vklb_status fold_partials(vklb_solver* s, hipStream_t st, int par) {
+  if (s->sd.nred == s->sd.nblocks) return VKLB_OK;
+  hipLaunchKernelGGL(k_fold_partials, dim3(1), dim3(1024), 0, st, s->sd, par);
+  HIPCHK(s, hipGetLastError());
+  return VKLB_OK;
+}
+
 vklb_status launch_steps(vklb_solver* s, hipStream_t st, long long n, long long first_launch) {
   SolveDesc d = s->sd;
   for (long long i = 0; i < n; ++i) {
     d.par = int((first_launch + i) & 1);
     HIPCHK(s, s->K.step(d, s->step_grid, st));
+    vklb_status r = fold_partials(s, st, d.par ^ 1);
+    if (r != VKLB_OK) return r;
   }
   return VKLB_OK;
 }
@@ -344,6 +387,11 @@ vklb_status vklb_create(const vklb_system* sys, vklb_lattice lat, const vklb_gri
   if (halo < 1 || halo > 32) halo = default_halo(sys->kind);
   s->sd = make_desc(s->buf, L, sys, &s->grid, lambda, omega, s->bc, eq, width, band, halo);
   s->step_grid = s->sd.nblocks;
+  // Grids of many workgroups: every workgroup reading every partial costs
+  // nblocks^2 loads per step (10^12 at a million workgroups), so above the
+  // threshold each launch's partials are folded into one entry instead.
+  const int fold = s->opt.fold_partials == 0 ? kFoldAbove : s->opt.fold_partials;
+  if (fold > 0 && s->sd.nblocks > fold) s->sd.nred = 1;
   // small 1D grids: whole step sequences in one workgroup (bitwise the same)
   if (grid->dim == 1 && s->opt.small_grid >= 0 && s->K.run_wg && grid->n[0] <= s->K.wg_max_cells) {
     const long long n = grid->n[0];
@@ -401,6 +449,8 @@ static vklb_status init_from(vklb_solver* s, const double* U0, hipMemcpyKind kin
   SolveDesc d = s->sd;
   d.par = 0;
   HIPCHK(s, s->K.init_reduce(d, d.nblocks, s->stream));
+  st = fold_partials(s, s->stream, 0);
+  if (st != VKLB_OK) return st;
   HIPCHK(s, s->K.init_feq(d, grid_for_cells(cells), s->stream));
   s->inited = true;
   return VKLB_OK;

@@ -54,7 +54,8 @@ class Equilibrium(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("basis", ctypes.c_int), ("band_rows", ctypes.c_int), ("graph_chunk", ctypes.c_int),
-                ("strip_width", ctypes.c_int), ("halo_rows", ctypes.c_int), ("small_grid", ctypes.c_int)]
+                ("strip_width", ctypes.c_int), ("halo_rows", ctypes.c_int), ("small_grid", ctypes.c_int),
+                ("fold_partials", ctypes.c_int)]
 
 
 class Diag(ctypes.Structure):
@@ -188,7 +189,7 @@ class Solver:
     """One WU-VKLB solve on the GPU (see include/vklb.h for the semantics)."""
 
     def __init__(self, problem, precision="fp64", basis=0, band_rows=0, graph_chunk=0, strip_width=0,
-                 stream=None, use_torch=True, halo_rows=0, small_grid=0):
+                 stream=None, use_torch=True, halo_rows=0, small_grid=0, fold_partials=0):
         self.problem = problem
         self.precision = precision
         self.p = problem.p
@@ -212,7 +213,7 @@ class Solver:
             sptr = st.cuda_stream
             self._stream = st
         opt = Options(int(basis), int(band_rows), int(graph_chunk), int(strip_width), int(halo_rows),
-                      int(small_grid))
+                      int(small_grid), int(fold_partials))
         h = ctypes.c_void_p()
         r = L.vklb_create(ctypes.byref(sysd), lat, ctypes.byref(grid), ctypes.byref(speed), float(problem.omega), bc,
                           ctypes.byref(eq), PRECISIONS[precision], ctypes.byref(opt), ptr, nbytes, sptr,

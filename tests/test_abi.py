@@ -183,3 +183,15 @@ def test_plain_c_program_uses_the_abi(vk, tmp_path):
     code, msg = got["create_bad_omega"].split(" ", 1)
     assert int(code) == vk.ERR_ARG and "omega" in msg
     assert got["solver_null"] == "1"
+
+
+def test_options_binding_matches_header(vk):
+    """The binding's vklb_options has the header's int fields in the header's order."""
+    import re
+    hdr = open(os.path.join(ROOT, "include", "vklb.h")).read()
+    end = hdr.index("} vklb_options;")
+    body = hdr[hdr.rindex("typedef struct {", 0, end):end]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\bint\s+(\w+)\s*;", body)
+    assert fields == [f[0] for f in vk.Options._fields_]
+    assert all(t is ctypes.c_int for _, t in vk.Options._fields_)
