@@ -156,6 +156,15 @@ inline vklb_status validate(const vklb_system* sys, vklb_lattice lat, const vklb
   return VKLB_OK;
 }
 
+// After a step launch (or the initial reduction) that left the partials of
+// parity `par`: fold them into entry 0 when the solve's launches read that
+// entry alone (nred = 1).
+inline hipError_t launch_fold(const SolveDesc& d, int par, hipStream_t s) {
+  if (d.nred == d.nblocks) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_partials<1024>, dim3(1), dim3(1024), 0, s, d, par);
+  return hipGetLastError();
+}
+
 // Kernel descriptor of a solve whose workspace starts at `base`.
 inline SolveDesc make_desc(char* base, const Layout& L, const vklb_system* sys, const vklb_grid* grid,
                            const vklb_speed* lambda, double omega, const vklb_bc bc[2], const vklb_equilibrium* eq,

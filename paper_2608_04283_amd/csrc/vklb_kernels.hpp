@@ -1029,6 +1029,40 @@ __global__ void __launch_bounds__(W) k_step_batched(const SolveDesc* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// One workgroup folds the per-workgroup maxima of parity `par` into entry 0
+// of each half (max |lambda|, max c_f). The max is exact and independent of
+// order, so a step launch that reads entry 0 alone derives the step every
+// workgroup would derive from all the entries. Eight loads per lane and
+// iteration keep enough of them in flight for a million workgroups.
+template <int LANES = 1024>
+__global__ void __launch_bounds__(LANES) k_fold_partials(const SolveDesc sd, int par) {
+  __shared__ double red[2 * (LANES / 64) + 2];
+  double* pl = sd.part + (long long)par * 2 * sd.nblocks;
+  const double* pc = pl + sd.nblocks;
+  const int nb = sd.nblocks;
+  double a = 0.0, b = 0.0;
+  for (int i0 = threadIdx.x; i0 < nb; i0 += 8 * LANES) {
+    double x[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * LANES;
+      x[u] = i < nb ? pl[i] : 0.0;
+      y[u] = i < nb ? pc[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a = fmax(a, x[u]);
+      b = fmax(b, y[u]);
+    }
+  }
+  block_max2_all<true>(a, b, red, LANES);
+  if (threadIdx.x == 0) {
+    pl[0] = a;
+    pl[nb] = b;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Initialization: (1) reduction of max|lambda| and max c_f over U0 (FP64
 // staging) giving xi^0, Lambda^0, c_h^0; (2) f_q = f_q^eq(U0) (Sec. 3.5).
 // ---------------------------------------------------------------------------

@@ -206,6 +206,7 @@ vklb_status admit(vklb_pool* p) {
     r->sd = make_desc(p->base + off, r->L, &r->sys, &r->grid, &r->speed, r->omega, r->bc, &r->eq, width, r->band,
                       default_halo(r->sys.kind));
     r->sd.npar = int(p->round & 1);  // step 0 runs at the parity of the next round
+    if (r->sd.nblocks > kFoldAbove) r->sd.nred = 1;  // as a single solve: partials folded after each round
     // initialization into the parity of the next round
     const long long cells = (long long)r->sd.nx * r->sd.ny;
     PCHK(p, hipMemcpyAsync(const_cast<double*>(r->sd.stage), r->U0.data(), r->U0.size() * 8, hipMemcpyHostToDevice,
@@ -222,6 +223,7 @@ vklb_status admit(vklb_pool* p) {
     d.par = int(p->round & 1);
     const Launchers& K = p->cls_launch[r->cls];
     PCHK(p, K.init_reduce(d, d.nblocks, p->stream));
+    PCHK(p, launch_fold(d, d.par, p->stream));
     PCHK(p, K.init_feq(d, grid_for_cells(cells), p->stream));
     p->dirty = true;
     p->stats.admitted++;
@@ -365,9 +367,14 @@ vklb_status vklb_pool_run(vklb_pool* p, int rounds) {
   for (int c = 0; c < kClasses; ++c) {
     if (!p->nwork[c]) continue;
     PCHK(p, hipStreamWaitEvent(p->cls_stream[c], p->ev_main, 0));
+    std::vector<const SolveDesc*> fold;  // this class's solves whose partials are folded
+    for (int i = 0; i < kMaxSlots; ++i)
+      if (p->slots[i] && p->slots[i]->cls == c && p->slots[i]->sd.nred != p->slots[i]->sd.nblocks)
+        fold.push_back(&p->slots[i]->sd);
     for (int k = 0; k < rounds; ++k) {
       const int par = int((p->round + k) & 1);
       PCHK(p, p->cls_launch[c].batched(p->d_descs, p->d_work[c], p->d_nwork + c, par, p->nwork[c], p->cls_stream[c]));
+      for (const SolveDesc* d : fold) PCHK(p, launch_fold(*d, par ^ 1, p->cls_stream[c]));
     }
     // ... and the caller's stream continues after every class's rounds
     PCHK(p, hipEventRecord(p->ev_cls[c], p->cls_stream[c]));

@@ -66,38 +66,6 @@ __global__ void k_totals_final(const double* __restrict__ part, int nblk, int p,
   out[v] = S + C;
 }
 
-// One workgroup folds the per-workgroup maxima of parity `par` into entry 0
-// of each half (max |lambda|, max c_f). The max is exact and independent of
-// order, so a launch that reads entry 0 alone derives the step every
-// workgroup would derive from all the entries. Eight loads per lane and
-// iteration keep enough of them in flight for a million workgroups.
-__global__ void __launch_bounds__(1024) k_fold_partials(const SolveDesc sd, int par) {
-  __shared__ double red[2 * 16 + 2];
-  double* pl = sd.part + (long long)par * 2 * sd.nblocks;
-  const double* pc = pl + sd.nblocks;
-  const int nb = sd.nblocks;
-  double a = 0.0, b = 0.0;
-  for (int i0 = threadIdx.x; i0 < nb; i0 += 8 * 1024) {
-    double x[8], y[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = i0 + u * 1024;
-      x[u] = i < nb ? pl[i] : 0.0;
-      y[u] = i < nb ? pc[i] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      a = fmax(a, x[u]);
-      b = fmax(b, y[u]);
-    }
-  }
-  block_max2_all<true>(a, b, red, 1024);
-  if (threadIdx.x == 0) {
-    pl[0] = a;
-    pl[nb] = b;
-  }
-}
-
 // max |dBx/dx + dBy/dy| by central differences on the FP64 moments; ghosts
 // follow the boundary rule (periodic wrap or copy of the boundary cell).
 __global__ void k_divb(const double* __restrict__ U, int nx, int ny, double dx, int bcx, int bcy,
@@ -226,9 +194,7 @@ vklb_status reset_state(vklb_solver* s, double t, long long n, int done) {
 // Folds the partials of parity `par` into entry 0 when the solve's step
 // launches read that entry alone.
 vklb_status fold_partials(vklb_solver* s, hipStream_t st, int par) {
-  if (s->sd.nred == s->sd.nblocks) return VKLB_OK;
-  hipLaunchKernelGGL(k_fold_partials, dim3(1), dim3(1024), 0, st, s->sd, par);
-  HIPCHK(s, hipGetLastError());
+  HIPCHK(s, launch_fold(s->sd, par, st));
   return VKLB_OK;
 }
 

@@ -98,3 +98,30 @@ def test_folded_partials_are_bitwise_the_direct_reduction(gpu, name, prec):
         assert np.array_equal(U, Ur) and (t, n) == (tr, nr)
         outs.append((U, t, n))
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]
+
+
+def test_folded_partials_in_the_pool(gpu, oracle):
+    """A solve above the folding threshold (2,363 workgroups) served next to a
+    small one: the same bits as alone, and the oracle's values."""
+    big = I.random_riemann("euler", 1, 600_000, seed=7, max_steps=12)
+    small = I.random_riemann("sw", 1, 3000, seed=8, max_steps=20)
+    pool = gpu.Pool(1 << 30, "fp32")
+    for i, P in enumerate((big, small)):
+        pool.submit(P, tag=i)
+    got = {}
+    while len(got) < 2:
+        pool.run(4)
+        for c in pool.poll():
+            got[c["tag"]] = c
+    pool.close()
+    for i, P in enumerate((big, small)):
+        s = gpu.Solver(P, precision="fp32")
+        s.init()
+        U, t, n = s.run()
+        s.close()
+        c = got[i]
+        assert c["status"] == 0 and c["steps"] == n == P.max_steps and c["t"] == t
+        assert np.array_equal(c["U"], U), P.name
+    ref = run_oracle(oracle, big)
+    assert ref["status"] == 0 and ref["steps"] == 12
+    assert np.all(rel_l1(got[0]["U"], ref["U"]) <= 1e-4)
