@@ -79,6 +79,52 @@ def profiled_traffic(workload, prec, cells_per_launch):
     return float(b.group(1))
 
 
+# Stored FP64 oracle results (written by tests/golden/make_oracle_goldens.py,
+# which runs the oracle alone) that each workload's final state is compared
+# with: the workload itself (1D), or the size its oracle comparison uses (2D),
+# which is then run on the GPU beside the timed solves.
+GOLDEN = {
+    "euler1d_sod": ("oracle_euler1d_sod_n65536.npz", None),
+    "sw1d_dambreak": ("oracle_sw1d_dambreak_d1q2_n1000.npz", None),
+    "mhd1d_briowu": ("oracle_mhd1d_briowu_n16384.npz", None),
+    "euler2d_quadrants": ("oracle_euler2d_quadrants_n512_s0.npz", lambda: I.quadrants(512, seed=0, steps=2000)),
+    "mhd2d_orszag_tang": ("oracle_mhd2d_orszag_tang_n256.npz", lambda: I.orszag_tang(256, steps=1000)),
+}
+
+
+def rel_l1(a, b, small=1e-3):
+    """Per field sum|a - b| / sum|b|; fields whose L1 norm is below `small`
+    times the largest field's (identically zero ones) are measured against
+    the largest field's norm."""
+    import numpy as np
+    num = np.abs(a - b).sum(axis=1)
+    den = np.abs(b).sum(axis=1)
+    den = np.where(den <= small * den.max(), den.max(), den)
+    return num / den
+
+
+def error_vs_oracle(name, prec, U_final):
+    """Relative L1 per field of the final state against the stored oracle run."""
+    import numpy as np
+    from paper_2608_04283_amd import vklb
+    fname, small = GOLDEN[name]
+    path = os.path.join(ROOT, "tests", "golden", fname)
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    U, size = U_final, None
+    if small is not None:
+        P = small()
+        s = vklb.Solver(P, precision=prec)
+        s.init()
+        U, _, _ = s.run()
+        s.close()
+        size = "x".join(str(v) for v in P.n)
+    err = rel_l1(U, ref["U"])
+    return {"rel_l1_per_field": [float(f"{e:.3g}") for e in err], "max": float(f"{err.max():.3g}"),
+            "at_size": size or "the workload's", "oracle": "FP64"}
+
+
 def step_kernel(P, steps):
     """The kernel that advances the workload and the steps one launch takes:
     1D grids of up to 1024 cells (256 for MHD) run up to 1024 steps per
@@ -125,6 +171,7 @@ def time_workload(name, prec, K, W, quick=False):
     wall = time.perf_counter() - wall0
     total_ms = e0.elapsed_time(e1)
     t_end, n_end, done = s.progress()
+    U_final, _, _ = s.moments()
     s.close()
     assert n_end == steps and done, (n_end, steps, done)
     cells = P.cells
@@ -139,7 +186,8 @@ def time_workload(name, prec, K, W, quick=False):
             "kernel": kernel, "avg_launch_us": round(step_time_ms * spl * 1e3, 3), "steps_per_launch": spl,
             "us_per_step": round(step_time_ms * 1e3, 3),
             "alg_bytes_per_cell_step": alg_bytes_per_cell_step(P, prec), "cells_per_launch": cells}
-    return {"workload": P.name, "value": value, "ms_per_solve": total_ms / K, "steps_per_solve": steps,
+    err = error_vs_oracle(name, prec, U_final)
+    return {"workload": P.name, "value": value, "ms_per_solve": total_ms / K, "steps_per_solve": steps, "error": err,
             "cells": cells, "t_end": t_end, "roofline": roof, "wall_s": wall, "dtype": "f32" if prec == "fp32" else "f64"}
 
 
@@ -245,6 +293,7 @@ def main():
                    "time_steps_per_solve": main_res["steps_per_solve"], "t_end": main_res["t_end"],
                    "lattice": "D1Q3" if "1d" in args.workload else "D2Q5", "omega": 1.0, "c": 0.05, "k": 2.0},
         "roofline": main_res["roofline"],
+        "error_vs_oracle": main_res["error"],
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
@@ -253,7 +302,7 @@ def main():
         if p2 != prec and not args.no_other_precision:
             r = time_workload(args.workload, p2, max(1, args.steps // 2), 1)
             extra[p2] = {"value": round(r["value"], 2), "ms_per_solve": round(r["ms_per_solve"], 4),
-                         "roofline": r["roofline"]}
+                         "roofline": r["roofline"], "error_vs_oracle": r["error"]}
     if extra:
         out["other_precision"] = extra
     if not args.no_also:
@@ -263,7 +312,8 @@ def main():
                 continue
             r = time_workload(name, wprecs[0], 2, 1)
             also[name] = {"value": round(r["value"], 2), "dtype": r["dtype"], "ms_per_solve": round(r["ms_per_solve"], 3),
-                          "steps_per_solve": r["steps_per_solve"], "roofline": r["roofline"]}
+                          "steps_per_solve": r["steps_per_solve"], "roofline": r["roofline"],
+                          "error_vs_oracle": r["error"]}
         out["also"] = also
     if args.serving_requests > 0:
         out["serving"] = serving_bench(args.serving_requests)
