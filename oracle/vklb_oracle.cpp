@@ -165,11 +165,14 @@ double mhd_cf(const or_config& cf, int d, const double* U) {
   double BB = U[5] * U[5] + U[6] * U[6] + U[7] * U[7];
   double p = (cf.gamma - 1.0) * (U[4] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) - 0.5 * BB);
   double a2 = cf.gamma * p / rho;
-  double b2 = BB / rho;
   double bd2 = U[5 + d] * U[5 + d] / rho;
-  double s = a2 + b2;
-  double disc = std::sqrt(std::max(0.0, s * s - 4.0 * a2 * bd2));
-  return std::sqrt(0.5 * (s + disc));
+  double bt2 = (BB - U[5 + d] * U[5 + d]) / rho;
+  // c_f^2 is the larger root of c^4 - (a^2 + b^2) c^2 + a^2 b_d^2 = 0. Its
+  // discriminant (a^2 + b^2)^2 - 4 a^2 b_d^2 is written as the sum of squares
+  // (a^2 - b_d^2)^2 + b_t^2 (2 a^2 + 2 b_d^2 + b_t^2): the difference form
+  // cancels to half the digits where a^2 = b_d^2 and b_t = 0 (the triple point).
+  double disc = std::sqrt((a2 - bd2) * (a2 - bd2) + bt2 * (2.0 * a2 + 2.0 * bd2 + bt2));
+  return std::sqrt(0.5 * (a2 + bd2 + bt2 + disc));
 }
 
 // Closed-form eigenvalues of dF^(d)/dU, in ascending order.

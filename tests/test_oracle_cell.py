@@ -377,3 +377,58 @@ def test_mhd_cleaning_pair_is_decoupled(oracle):
         assert np.all(A[np.ix_(rows, other)] == 0.0)
         sub = A[np.ix_(rows, rows)]
         assert np.allclose(np.sort(np.linalg.eigvals(sub).real), [-ch, ch])
+
+
+@pytest.mark.parametrize("deg", [None, "bt0", "bt_small", "triple_near", "bx0"])
+def test_fast_speed_is_the_fast_eigenvalue_of_the_jacobian(oracle, deg):
+    """Sec. 5.3: the fast magnetosonic speed c_f sets the cleaning speed
+    c_h = 6 max c_f, and through it Lambda, xi and every weight of an MHD run.
+    The oracle computes it by a formula of its own (fast_speed), apart from
+    the closed-form eigenvalues. It must equal the largest eigenvalue of the
+    flux Jacobian less u_d (and u_d less the smallest), once the cleaning
+    pair +-c_h, put far outside the physical speeds, is set aside. The
+    Jacobian comes from complex-step differentiation of the flux, so this
+    checks the formula against the system itself, not against itself."""
+    O = oracle
+    rng = np.random.default_rng(23)
+    for dim in (1, 2):
+        cf = cfg(O, "mhd", dim)
+        for _ in range(20):
+            U = rand_state("mhd", dim, rng, degenerate=deg)
+            for d in range(dim):
+                c_f = O.fast_speed(cf, d, U)
+                ch = 1e3 * (c_f + 10.0)
+                ev = np.sort(np.linalg.eigvals(O.jacobian(cf, d, U, ch)).real)
+                assert ev[0] < -0.9 * ch and ev[-1] > 0.9 * ch
+                phys = ev[1:-1]
+                ud = U[1 + d] / U[0]
+                assert abs(phys[-1] - ud - c_f) <= 1e-12 * c_f, (deg, phys[-1] - ud, c_f)
+                assert abs(ud - phys[0] - c_f) <= 1e-12 * c_f, (deg, ud - phys[0], c_f)
+
+
+def test_fast_speed_textbook_limits(oracle):
+    """Sec. 5.3, the fast speed in its textbook limits (mu_0 = 1): no field,
+    the sound speed a; field along d only, max(a, |B_d|/sqrt(rho)); field
+    across d only, sqrt(a^2 + |B|^2/rho); at the triple point (field along d
+    with B_d^2/rho = a^2), where three speeds meet and a numerical eigensolver
+    loses half its digits, a itself."""
+    O = oracle
+    cf = cfg(O, "mhd", 2)
+    gamma = 2.0
+    rng = np.random.default_rng(29)
+    for _ in range(20):
+        rho, p = rng.uniform(0.3, 2.0), rng.uniform(0.1, 2.0)
+        u, v, w = rng.uniform(-1, 1, 3)
+        a = math.sqrt(gamma * p / rho)
+        b = rng.uniform(0.2, 1.5)
+        cases = [
+            ((0.0, 0.0, 0.0), 0, a),
+            ((b, 0.0, 0.0), 0, max(a, b / math.sqrt(rho))),
+            ((0.0, b, 0.0), 1, max(a, b / math.sqrt(rho))),
+            ((0.0, b, 0.7 * b), 0, math.sqrt(a * a + 1.49 * b * b / rho)),
+            ((0.6 * b, 0.0, 0.8 * b), 1, math.sqrt(a * a + b * b / rho)),
+            ((math.sqrt(gamma * p), 0.0, 0.0), 0, a),
+        ]
+        for B, d, want in cases:
+            U = I.mhd_state(np.array([rho]), u, v, w, p, B[0], B[1], B[2], gamma)[:, 0]
+            assert abs(O.fast_speed(cf, d, U) - want) <= 1e-14 * want, (B, d)
