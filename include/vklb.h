@@ -249,6 +249,54 @@ vklb_status vklb_tune(const vklb_system* sys, vklb_lattice lat, const vklb_grid*
                       vklb_options* best, double* best_step_us);
 
 /* ------------------------------------------------------------------------
+ * Allocation-free solve, for callers that cannot allocate device memory:
+ * code being captured into a HIP graph, serving loops that forbid
+ * allocation, harnesses that do not allow hipMalloc.
+ *
+ * vklb_run_static does what vklb_create (default options, no graph chunks)
+ * + vklb_set_end(T, n_steps) + vklb_init_device + vklb_step(n_steps) + the
+ * moments of vklb_moments do, with the same kernels and so the same bits,
+ * but its workspace is a fixed array of VKLB_STATIC_BYTES inside the library
+ * (one per GPU, held from the library's first use on that GPU until the
+ * process ends). It calls no hipMalloc, hipFree or other allocating routine
+ * and does not synchronize: everything is enqueued on hip_stream, in order.
+ *
+ *  U0_device   FP64 SoA [p][cells] in device memory: the initial state (read).
+ *  U_device    FP64 SoA [p][cells] in device memory: U after the run (written).
+ *  info_device device memory for one vklb_run_info (written; may be NULL):
+ *              time, steps taken, whether the end was reached, and the step
+ *              and cell of a non-physical state (-1 if none).
+ *  T, n_steps  end time (INFINITY: none) and number of step launches; steps
+ *              past T are no-ops, and the step that reaches T lands on it.
+ *
+ * Errors (before anything is enqueued): VKLB_ERR_ARG for NULL arrays,
+ * n_steps < 0, T = NaN or any argument vklb_create rejects; VKLB_ERR_OOM when
+ * the solve's workspace (vklb_workspace_bytes of the same arguments) exceeds
+ * VKLB_STATIC_BYTES; VKLB_ERR_DEVICE when a launch fails. The message is
+ * left for vklb_last_error(NULL).
+ *
+ * Every call on one GPU shares that GPU's array and overwrites what the
+ * previous call left there (every value a run reads is written by the run
+ * first). Calls that overlap on one GPU (on two streams, or from two
+ * threads) race on the array and give undefined results: serialize them.
+ * ------------------------------------------------------------------------ */
+#define VKLB_STATIC_BYTES (64u * 1024u * 1024u)
+
+typedef struct {
+  double t;            /* time reached */
+  int64_t steps;       /* steps taken */
+  int64_t fail_step;   /* step that produced a non-physical state (-1 if none) */
+  int64_t fail_cell;   /* lowest cell where it was seen (-1 if none) */
+  int done;            /* end time or n_steps reached, or stopped by a non-physical state */
+  int nonphysical;     /* 1 if a non-physical state was produced */
+} vklb_run_info;
+
+vklb_status vklb_run_static(const vklb_system* sys, vklb_lattice lat, const vklb_grid* grid,
+                            const vklb_speed* lambda, double omega, const vklb_bc bc[2], const vklb_equilibrium* eq,
+                            vklb_precision prec, double T, int64_t n_steps, const double* U0_device,
+                            double* U_device, vklb_run_info* info_device, void* hip_stream);
+
+/* ------------------------------------------------------------------------
  * Serving: a pool of concurrent solves in one device arena.
  *
  * Requests are admitted in submission order when their workspace fits in

@@ -7,8 +7,6 @@
 #include <math.h>
 #include <string.h>
 
-#include <string>
-
 #include "../../include/vklb.h"
 #include "vklb_launch.hpp"
 
@@ -112,7 +110,7 @@ inline int step_grid_of(const vklb_grid* g, int width, int band) {
 // Sec. 3.4 dx == dy). Returns VKLB_OK or an error with a message.
 inline vklb_status validate(const vklb_system* sys, vklb_lattice lat, const vklb_grid* grid, const vklb_speed* lambda,
                             double omega, const vklb_bc bc[2], const vklb_equilibrium* eq, vklb_precision prec,
-                            std::string* msg) {
+                            const char** msg) {
   auto bad = [&](vklb_status st, const char* m) { *msg = m; return st; };
   if (!sys || !grid || !lambda || !bc || !eq) return bad(VKLB_ERR_ARG, "NULL argument");
   if (sys->kind < VKLB_SHALLOW_WATER || sys->kind > VKLB_LINEAR) return bad(VKLB_ERR_ARG, "unknown system");

@@ -320,7 +320,7 @@ vklb_status vklb_pool_create(size_t hbm_budget, vklb_precision prec, void* hip_s
 
 vklb_status vklb_pool_submit(vklb_pool* p, const vklb_request* rq, uint64_t* ticket) {
   if (!p || !rq || !rq->U0 || !rq->U_out) return VKLB_ERR_ARG;
-  std::string msg;
+  const char* msg = "";
   vklb_status st = validate(&rq->sys, rq->lat, &rq->grid, &rq->lambda, rq->omega, rq->bc, &rq->eq, p->prec, &msg);
   if (st != VKLB_OK) return pfail(p, st, msg);
   if (!isfinite(rq->T) && rq->max_steps < 0) return pfail(p, VKLB_ERR_ARG, "a request needs an end time or a step limit");

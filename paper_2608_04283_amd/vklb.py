@@ -25,7 +25,9 @@ EQ_SETS = {"weighted": 0, "centered": 1, "discontinuous": 2}
 EXPORTED = ["vklb_workspace_bytes", "vklb_create", "vklb_set_end", "vklb_init", "vklb_init_device", "vklb_step", "vklb_moments",
             "vklb_progress", "vklb_diagnostics", "vklb_state_bytes", "vklb_get_state", "vklb_set_state", "vklb_last_step_ms",
             "vklb_destroy", "vklb_status_str", "vklb_last_error", "vklb_pool_create", "vklb_pool_submit",
-            "vklb_pool_run", "vklb_pool_poll", "vklb_pool_get_stats", "vklb_pool_destroy", "vklb_tune"]
+            "vklb_pool_run", "vklb_pool_poll", "vklb_pool_get_stats", "vklb_pool_destroy", "vklb_tune",
+            "vklb_run_static"]
+STATIC_BYTES = 64 * 1024 * 1024  # VKLB_STATIC_BYTES
 
 
 class VklbError(RuntimeError):
@@ -74,6 +76,11 @@ class Request(ctypes.Structure):
 class Completion(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int), ("t", ctypes.c_double),
                 ("steps", ctypes.c_int64), ("fail_step", ctypes.c_int64), ("fail_cell", ctypes.c_int64)]
+
+
+class RunInfo(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("steps", ctypes.c_int64), ("fail_step", ctypes.c_int64),
+                ("fail_cell", ctypes.c_int64), ("done", ctypes.c_int), ("nonphysical", ctypes.c_int)]
 
 
 class PoolStats(ctypes.Structure):
@@ -134,6 +141,10 @@ def lib():
     L.vklb_tune.argtypes = [ctypes.POINTER(System), ctypes.c_int, ctypes.POINTER(Grid), ctypes.POINTER(Speed),
                             ctypes.c_double, ctypes.c_int * 2, ctypes.POINTER(Equilibrium), ctypes.c_int,
                             ctypes.POINTER(Options), dp, ctypes.c_int, vp, ctypes.POINTER(Options), dp]
+    L.vklb_run_static.argtypes = [ctypes.POINTER(System), ctypes.c_int, ctypes.POINTER(Grid), ctypes.POINTER(Speed),
+                                  ctypes.c_double, ctypes.c_int * 2, ctypes.POINTER(Equilibrium), ctypes.c_int,
+                                  ctypes.c_double, ctypes.c_int64, vp, vp, vp, vp]
+    L.vklb_run_static.restype = ctypes.c_int
     for name in ("vklb_pool_create", "vklb_pool_submit", "vklb_pool_run", "vklb_pool_poll", "vklb_pool_get_stats"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("vklb_create", "vklb_set_end", "vklb_init", "vklb_init_device", "vklb_step", "vklb_moments", "vklb_progress",
@@ -183,6 +194,29 @@ def tune(problem, precision="fp32", steps=20, basis=0, stream=None):
         raise VklbError(r, L.vklb_last_error(None).decode())
     return ({"basis": best.basis, "strip_width": best.strip_width, "band_rows": best.band_rows,
              "halo_rows": best.halo_rows, "graph_chunk": best.graph_chunk, "small_grid": best.small_grid}, us.value)
+
+
+def run_static(problem, precision, n_steps, U0_dev_ptr, U_dev_ptr, info_dev_ptr=None, stream=None, T=None):
+    """vklb_run_static: the whole solve (init, n_steps step launches, moments)
+    in the library's fixed workspace, enqueued on `stream` (a torch stream, or
+    an int hipStream_t; None: torch's current stream). The arrays are device
+    pointers (FP64 SoA [p][cells]); info_dev_ptr points to device memory for
+    one RunInfo (or None). T defaults to the problem's end time."""
+    L = lib()
+    sysd, lat, grid, speed, eq, bc = _structs(problem)
+    if T is None:
+        T = problem.T if problem.T is not None else math.inf
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    sptr = stream if isinstance(stream, int) else stream.cuda_stream
+    r = L.vklb_run_static(ctypes.byref(sysd), lat, ctypes.byref(grid), ctypes.byref(speed), float(problem.omega), bc,
+                          ctypes.byref(eq), PRECISIONS[precision], float(T), int(n_steps),
+                          ctypes.c_void_p(int(U0_dev_ptr)) if U0_dev_ptr else None,
+                          ctypes.c_void_p(int(U_dev_ptr)) if U_dev_ptr else None,
+                          ctypes.c_void_p(int(info_dev_ptr)) if info_dev_ptr else None, ctypes.c_void_p(sptr))
+    if r != OK:
+        raise VklbError(r, L.vklb_last_error(None).decode())
 
 
 class Solver:

@@ -195,3 +195,38 @@ def test_options_binding_matches_header(vk):
     fields = re.findall(r"\bint\s+(\w+)\s*;", body)
     assert fields == [f[0] for f in vk.Options._fields_]
     assert all(t is ctypes.c_int for _, t in vk.Options._fields_)
+
+
+def run_static_raw(vk, P, precision="fp64", n_steps=10, U0=1, U=1, T=math.inf, **over):
+    """vklb_run_static with fake device pointers: every case here is rejected
+    before anything is enqueued, so the pointers are never used."""
+    sysd, lat, grid, speed, eq, bc = vk._structs(P)
+    for k, v in over.items():
+        obj, field = k.split(".")
+        setattr({"sys": sysd, "grid": grid, "speed": speed, "eq": eq}[obj], field, v)
+    L = vk.lib()
+    r = L.vklb_run_static(ctypes.byref(sysd), lat, ctypes.byref(grid), ctypes.byref(speed), P.omega, bc,
+                          ctypes.byref(eq), vk.PRECISIONS[precision], T, n_steps,
+                          ctypes.c_void_p(U0) if U0 else None, ctypes.c_void_p(U) if U else None, None, None)
+    return r, L.vklb_last_error(None).decode()
+
+
+@pytest.mark.parametrize("case,status,needle", [
+    ({"U0": 0}, "ERR_ARG", "NULL"),
+    ({"U": 0}, "ERR_ARG", "NULL"),
+    ({"n_steps": -1}, "ERR_ARG", "n_steps"),
+    ({"T": math.nan}, "ERR_ARG", "NaN"),
+    ({"speed.nu": 1.5}, "ERR_ARG", "nu"),
+    ({"grid.n": None}, "ERR_OOM", "static"),
+])
+def test_run_static_rejects_before_enqueueing(vk, case, status, needle):
+    """The allocation-free entry point checks its arguments and the static
+    workspace's size before it touches the GPU."""
+    P = I.sod(1000)
+    if "grid.n" in case:
+        # Euler 1D FP64 at 2^21 cells needs ~170 MB, above the 64 MiB array
+        P = I.sod(1 << 21)
+        case = {}
+        assert vk.workspace_bytes(P, "fp64") > vk.STATIC_BYTES
+    r, msg = run_static_raw(vk, P, **case)
+    assert r == getattr(vk, status) and needle in msg, (r, msg)
