@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 from paper_2608_04283_amd import inputs as I
-from parity_util import rel_l1, run_oracle
+from parity_util import check_fields, rel_l1, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -22,13 +22,15 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 CASES = [
     # (golden name, problem factory, precision, tolerance on relative L1 per field)
     ("sw1d_dambreak_d1q2_n1000", lambda: I.dam_break(1000, c=0.5, k=0.0), "fp64", 1e-12),
-    ("sw1d_dambreak_wu_n1000_100steps", lambda: I.dam_break(1000, max_steps=100), "fp64", 1e-12),
+    ("sw1d_dambreak_wu_n1000", lambda: I.dam_break(1000), "fp64", 1e-12),
     ("euler1d_sod_n65536", lambda: I.sod(65536), "fp64", 1e-12),
     ("euler1d_sod_n65536", lambda: I.sod(65536), "fp32", 1e-4),
     ("euler1d_wave_n256", lambda: I.smooth_wave(256), "fp64", 1e-12),
     ("euler1d_wave_n1024", lambda: I.smooth_wave(1024), "fp64", 1e-12),
     ("euler1d_wave_n4096", lambda: I.smooth_wave(4096), "fp64", 1e-12),
     ("euler1d_wave_n4096", lambda: I.smooth_wave(4096), "fp32", 1e-4),
+    ("euler1d_wave_n16384", lambda: I.smooth_wave(16384), "fp64", 1e-12),
+    ("euler1d_wave_n16384", lambda: I.smooth_wave(16384), "fp32", 1e-4),
     ("euler2d_quadrants_n512_s0", lambda: I.quadrants(512, seed=0, steps=2000), "fp32", 1e-4),
     ("mhd2d_orszag_tang_n256", lambda: I.orszag_tang(256, steps=1000), "fp32", 1e-4),
     ("mhd1d_briowu_n16384", lambda: I.brio_wu(16384), "fp32", 1e-4),
@@ -57,39 +59,33 @@ def test_config_full_length(gpu, name, factory, prec, tol):
     assert np.all(err <= tol), err
 
 
-@pytest.mark.parametrize("factory,steps", [(lambda: I.quadrants(2048, seed=0, steps=2000), 3),
-                                           (lambda: I.orszag_tang(1024, steps=1000), 2)],
+@pytest.mark.parametrize("factory,steps,at_floor", [(lambda: I.quadrants(2048, seed=0, steps=2000), 3, ()),
+                                                    (lambda: I.orszag_tang(1024, steps=1000), 2, (8,))],
                          ids=["euler2d_quadrants_n2048", "mhd2d_orszag_tang_n1024"])
-def test_full_size_first_steps(gpu, oracle, factory, steps):
-    """At the benchmark sizes, in the benchmark's launch configuration."""
+def test_full_size_first_steps(gpu, oracle, factory, steps, at_floor):
+    """At the benchmark sizes, in the benchmark's launch configuration.
+
+    Orszag-Tang's cleaning potential psi (field 8) starts at zero, and after
+    two steps at 1024^2 it is of order 1e-8, while each of its populations
+    carries about nu c_h B_d / 2 ~ 1.5 (the psi flux is c_h^2 B_d): FP32
+    storage rounds those to ~1e-7, above psi itself, so psi is checked
+    against its rounding floor (parity_util.rounding_floor) and every other
+    field against 1e-5 of its own norm."""
     P = factory().with_(max_steps=steps)
     s = gpu.Solver(P, precision="fp32")
     s.init()
     U, t, n = s.run()
     s.close()
-    ref = run_oracle(oracle, P)
+    ref = run_oracle(oracle, P, want_f=bool(at_floor))
     assert n == ref["steps"] == steps
-    err = rel_l1(U, ref["U"])
-    print(f"[full] {P.name} steps={n} rel_l1={np.array2string(err, precision=2)}", flush=True)
-    assert np.all(err <= 1e-5), err
-    # the FP32 path stays within FP32 rounding of the FP64 oracle cell by cell
-    # (fields that are zero, or nearly, are scaled by the largest field)
+    err, abs_err = check_fields(U, ref["U"], 1e-5, "fp32", at_floor, ref.get("f"), steps)
+    print(f"[full] {P.name} steps={n} rel_l1={np.array2string(err, precision=2)} "
+          f"abs_l1={np.array2string(abs_err, precision=2)}", flush=True)
+    # cell by cell, the FP32 path stays within FP32 rounding of the FP64
+    # oracle, relative to each field's largest value (identically zero fields:
+    # the largest field's); fields at their floor are left to the check above
     peak = np.abs(ref["U"]).max(axis=1, keepdims=True)
-    scale = np.where(peak < 1e-3 * peak.max(), peak.max(), peak)
-    assert np.max(np.abs(U - ref["U"]) / scale) < 1e-5
-
-
-def test_mhd2d_orszag_tang_diagnostics(gpu):
-    """Sec. 5.3 problem family at the configuration's size: totals conserved on
-    the periodic grid, max|div B| reported (0 initially)."""
-    P = I.orszag_tang(1024, steps=1000)
-    s = gpu.Solver(P, precision="fp32")
-    s.init()
-    d0 = s.diagnostics()
-    s.step(1000)
-    d1 = s.diagnostics()
-    s.close()
-    assert d0["max_div_b"] < 1e-9 and d1["steps"] == 1000
-    assert np.isfinite(d1["max_div_b"]) and d1["max_div_b"] > 0
-    scale = np.abs(P.U0).sum(axis=1) + 1e-3 * np.abs(P.U0).sum()
-    assert np.all(np.abs(d1["totals"] - d0["totals"]) / scale < 1e-5)
+    scale = np.where(peak <= 1e-12 * peak.max(), peak.max(), peak)
+    cellwise = (np.abs(U - ref["U"]) / scale).max(axis=1)
+    keep = [v for v in range(P.p) if v not in at_floor]
+    assert np.all(cellwise[keep] < 1e-5), cellwise

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2608_04283_amd import inputs as I
-from parity_util import rel_l1, run_oracle
+from parity_util import check_fields, rel_l1, run_oracle
 from test_oracle_boundaries import acoustic_pulse, linear1d
 
 pytestmark = pytest.mark.gpu
@@ -60,6 +60,11 @@ CASES = {
     "euler1d_sod_char_fp32": (lambda: I.sod(1500, bc=("characteristic", "characteristic")), "fp32", {}),
     "euler1d_pulse_char_fp64": (lambda: acoustic_pulse(400, 0.0, 1.0, 0.6), "fp64", {}),
     "euler1d_pulse_char_fp32_delta": (lambda: acoustic_pulse(400, 0.0, 1.0, 0.6), "fp32", {"basis": 2}),
+    # a strong pulse half way through the right boundary: rho u is well above
+    # its rounding floor, so every field is held to the relative tolerance
+    "euler1d_pulse_strong_char_fp64": (lambda: acoustic_pulse(400, 0.0, 1.0, 0.3, eps=0.2), "fp64", {}),
+    "euler1d_pulse_strong_char_fp32_delta": (lambda: acoustic_pulse(400, 0.0, 1.0, 0.3, eps=0.2), "fp32",
+                                             {"basis": 2}),
     "sw1d_dambreak_char_fp64": (lambda: I.dam_break(1000, bc=("characteristic", "characteristic"), T=0.2), "fp64",
                                 {}),
     "linear1d_char_fp64": (lambda: linear1d(300, 0.7, 2.0, 400, "characteristic"), "fp64", {}),
@@ -116,12 +121,20 @@ CASES = {
 }
 
 
+# Fields checked against their rounding floor (parity_util.rounding_floor)
+# instead of a relative tolerance: after the weak pulse has left (t = 0.6)
+# rho u is a residual of 7e-8 of the energy's L1 norm, at the rounding level
+# of the resting gas's populations in either precision.
+AT_FLOOR = {"euler1d_pulse_char_fp64": (1,), "euler1d_pulse_char_fp32_delta": (1,)}
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_parity_with_oracle(gpu, oracle, name):
     factory, prec, opts = CASES[name]
     P = factory()
+    at_floor = AT_FLOOR.get(name, ())
     print(f"[case] {name} n={P.n} prec={prec} opts={opts}", flush=True)
-    ref = run_oracle(oracle, P)
+    ref = run_oracle(oracle, P, want_f=bool(at_floor))
     assert ref["status"] == 0
     s = gpu.Solver(P, precision=prec, **opts)
     s.init()
@@ -134,9 +147,9 @@ def test_parity_with_oracle(gpu, oracle, name):
     else:
         assert abs(n - ref["steps"]) <= 1
         assert abs(t - ref["t"]) <= 1e-6 * max(1.0, abs(ref["t"]))
-    err = rel_l1(U, ref["U"])
-    print(f"[case] {name} steps={n} rel_l1={np.array2string(err, precision=2)}", flush=True)
-    assert np.all(err <= TOL[prec]), err
+    err, abs_err = check_fields(U, ref["U"], TOL[prec], prec, at_floor, ref.get("f"), n)
+    print(f"[case] {name} steps={n} rel_l1={np.array2string(err, precision=2)}"
+          + (f" abs_l1={np.array2string(abs_err, precision=2)}" if at_floor else ""), flush=True)
 
 
 @pytest.mark.parametrize("prec,basis", [("fp64", 0), ("fp32", 0), ("fp32", 3)])
