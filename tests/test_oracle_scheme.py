@@ -241,6 +241,30 @@ def test_dam_break_converges_to_exact(oracle):
     assert np.all(rates > 0.5) and np.all(rates < 1.1)
 
 
+def test_weighted_dam_break_grows_at_the_rarefaction_head(oracle):
+    """At the dam break's nu = 1/1.2 the weighted split is past its limit at
+    rest (the U-dependent weights raise the split's numerical viscosity at a
+    resting state beyond the explicit update's bound, as for Euler gas at
+    rest). The left state is at rest up to the rarefaction head (x = 0.057 at
+    t = 0.1), and over the ~10^4 steps of a 16,000-cell run rounding there
+    grows to an O(0.1) error in h: the L1 error at N = 16,000 exceeds the one
+    at 4,000, and the excess sits at the head."""
+    O = oracle
+    ex = ShallowWaterRiemann(2.0, 0.0, 1.0, 0.0, 9.81)
+    sampler = lambda s: np.stack(ex.sample(s))
+    out = {}
+    for n in (4000, 16000):
+        P = I.dam_break(n)
+        r = O.run(cfg_of(O, P), P.U0)
+        assert r["status"] == 0 and r["t"] == 0.1
+        hu = cell_average_exact(sampler, np.linspace(0, 1, n + 1), r["t"], 0.5, sub=4)
+        x = (np.arange(n) + 0.5) / n
+        out[n] = (np.abs(r["U"][0] - hu[0]), x)
+    assert out[16000][0].mean() > out[4000][0].mean()
+    head = {n: e[(x > 0.04) & (x < 0.08)].max() for n, (e, x) in out.items()}
+    assert head[16000] > 0.1 and head[16000] > 5 * head[4000]
+
+
 def test_sod_converges_to_exact(oracle):
     """Sod tube (Sec. 5.2 table): L1 error against the exact solution falls
     with N at the rate of a first-order scheme across a contact
