@@ -133,7 +133,8 @@ typedef struct {
                           (FP32 only; VKLB_ERR_ARG with FP64);
                        0: default: FP64 -> 1; FP32 -> 3 in 1D, 2 in 2D.
                        Other values: VKLB_ERR_ARG. */
-  int band_rows;    /* 2D: rows per workgroup band (8..64); 0 = tuned default */
+  int band_rows;    /* 2D: rows per workgroup band (MHD in the delta bases: at most 64, larger values
+                       are taken as 64); 0 = tuned default */
   int graph_chunk;  /* steps captured per HIP graph (0 = 512; < 0: plain launches) */
   int strip_width;  /* 2D: columns per workgroup (64, 128 or 256); 1D: lanes per workgroup
                        (256 or 512, each finishing W - 2 cells); 0 = tuned default */
@@ -338,7 +339,18 @@ typedef struct {
   int64_t submitted, admitted, completed, queued, resident;
   int64_t rounds;
   size_t arena_bytes, arena_used, arena_peak;
+  int64_t graph_launches;  /* class round chunks replayed from a captured HIP graph */
+  int64_t graph_captures;  /* class round chunks captured */
 } vklb_pool_stats;
+
+/* One tuned 2D shape of the pool (vklb_pool_autotune). */
+typedef struct {
+  int kind;           /* vklb_system_kind */
+  int64_t n;          /* grid side of the sample it was tuned on */
+  int size_class;     /* round(2 log2 n): the grids that use it are those of the nearest class */
+  int band_rows, halo_rows;
+  double step_us;     /* the sample's time per step in that shape, alone */
+} vklb_pool_tile;
 
 /* hbm_budget: bytes of the device arena (allocated here); prec: precision of
  * every solve in the pool; hip_stream may be NULL. */
@@ -351,7 +363,31 @@ vklb_status vklb_pool_run(vklb_pool* p, int rounds);
  * count in *n; the rest are kept for the next call) and free their memory. */
 vklb_status vklb_pool_poll(vklb_pool* p, vklb_completion* out, int max, int* n);
 vklb_status vklb_pool_get_stats(const vklb_pool* p, vklb_pool_stats* st);
+/* Tile shapes of the batched 2D kernel (128-column strips; band and halo
+ * heights) by the autotuner (vklb_tune over those shapes), once per sample
+ * request: each 2D sample is timed alone for `steps` steps per candidate and
+ * its fastest shape is kept for its (system, half-octave size class of n);
+ * later admissions take the entry of their class, or the nearest tuned class
+ * of their system. The entries are kept for the process (per device and
+ * precision), so pools created later use them too. 1D samples are skipped
+ * (the batched 1D kernel has one shape). Call it before any request is
+ * submitted to this pool (VKLB_ERR_STATE otherwise),
+ * so that no other work disturbs the timing. Synchronizes; allocates one
+ * workspace per sample for the duration of its tuning. Up to *n_out entries
+ * are written to out (may be NULL); *n_out receives the count. */
+vklb_status vklb_pool_autotune(vklb_pool* p, const vklb_request* samples, int n, int steps, vklb_pool_tile* out,
+                               int* n_out);
 void vklb_pool_destroy(vklb_pool* p);
+
+/* Measurement utility (not a step of the method): copies `bytes` from src to
+ * dst, both device memory, with one streaming kernel that reads and writes
+ * every byte once, 16 bytes per lane access (non_temporal != 0: the
+ * non-temporal loads and stores the step kernels use for their populations).
+ * Enqueued on hip_stream; no sync. It gives the copy ceiling that the step
+ * kernels' HBM bandwidth is compared with, and a kernel of known traffic for
+ * scaling hardware byte counters. VKLB_ERR_ARG for NULL pointers or a size or
+ * address that is not a multiple of 16. */
+vklb_status vklb_stream_copy(void* dst, const void* src, size_t bytes, int non_temporal, void* hip_stream);
 
 const char* vklb_status_str(vklb_status st);
 const char* vklb_last_error(const vklb_solver* s); /* s may be NULL: last create error */

@@ -97,6 +97,9 @@ inline int default_width(int dim, long long nx) {
 // Rows per 2D band: MHD holds so many registers that only two workgroups fit a
 // compute unit, so it takes short bands to have enough of them.
 inline int default_band(int kind) { return kind == VKLB_MHD_GLM ? 8 : 32; }
+// Largest band: the MHD march of the delta bases collides a band's halo cells
+// into LDS for up to 64 rows; the others take any height.
+inline int max_band(int kind, int dim, int basis) { return kind == VKLB_MHD_GLM && dim == 2 && basis >= 1 ? 64 : 4096; }
 // Rows of halo columns per batch (1..32): measured fastest on MI355X with the
 // default bands, one batch per band (MHD 8 rows; the others 32, 3% over 2).
 inline int default_halo(int kind) { return kind == VKLB_MHD_GLM ? 8 : 32; }
@@ -218,6 +221,12 @@ inline Launchers pick_launchers(int kind, int dim, int prec, int basis, int widt
     default: return launchers_linear(dim, prec, basis, width);
   }
 }
+
+// Fastest band and halo heights of the serving pool's batched 2D kernel for
+// the solve of request r (vklb_tune over 128-column strips); defined with
+// vklb_tune.
+vklb_status tune_pool_shape(const vklb_request* r, vklb_precision prec, int steps, void* hip_stream, int* band,
+                            int* halo, double* step_us);
 
 inline int grid_for_cells(long long cells) {
   long long g = (cells + 255) / 256;

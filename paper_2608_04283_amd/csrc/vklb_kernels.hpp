@@ -421,6 +421,31 @@ struct Kern {
     for (int v = 0; v < P; ++v) out[v] = fq[v] - om * (fq[v] - T(plus ? fp[v] : fm[v]));
   }
 
+  // One stored slot (p values) of a strip row, non-temporal (see load_stream).
+  __device__ static inline void load_slot_stream(const T* __restrict__ src, long long cell, int slot, T (&f)[P]) {
+#pragma unroll
+    for (int v = 0; v < P; ++v) f[v] = __builtin_nontemporal_load(&src[pidx(slot * P + v, cell)]);
+  }
+
+  // Delta bases, 2D: both post-collision populations of axis AXIS (+AXIS
+  // from fplus, -AXIS from fminus) with one split of that axis; bitwise what
+  // relax gives for them.
+  template <int AXIS>
+  __device__ static inline void relax_axis(const T (&Ur)[P], const T (&fplus)[P], const T (&fminus)[P],
+                                           const Phys& ph, double ixi, double Lam, double ch, T (&outp)[P],
+                                           T (&outm)[P]) {
+    ST Us[P], fp[P], fm[P];
+#pragma unroll
+    for (int v = 0; v < P; ++v) Us[v] = ST(Ur[v]);
+    Equilibrium<KIND, DIM, ST>::eval_axis(Us, ph, ST(ixi), ST(Lam), ST(ch), AXIS, fp, fm);
+    const T om = T(ph.omega);
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+      outp[v] = fplus[v] - om * (fplus[v] - T(fp[v]));
+      outm[v] = fminus[v] - om * (fminus[v] - T(fm[v]));
+    }
+  }
+
   // U of a stored cell: the rest slot in the delta bases, else the sum of
   // the populations (in the order relax takes them).
   __device__ static inline void moments_of(const T* __restrict__ src, long long cell, T (&U)[P]) {
@@ -784,7 +809,7 @@ __global__ void __launch_bounds__(B) k_step1d(const SolveDesc sd) {
 // halo and next-row loads (2-3% per step on MI355X at 2048^2 and 1024^2).
 // ---------------------------------------------------------------------------
 template <int KIND, class T, int BASIS, int W>
-__device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
+__device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
   using K = Kern<KIND, 2, T, BASIS>;
   constexpr bool DELTA = K::DELTA;
   constexpr int P = K::P, Q = 5, REST = 2;
@@ -997,6 +1022,194 @@ __device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
   if (x < nx) finish(nr - 1);
   block_max2<KIND == K_MHD>(lam, cfm, red_end, W);
   end_step(sd, S, tile, lam, cfm);
+}
+
+// ---------------------------------------------------------------------------
+// 2D step of the delta bases for MHD, whose per-cell split holds most of the
+// registers: a row's two axes are split at different points of its march
+// iteration, and the row before it is finished in between, so the values a
+// lane keeps live never include both axes' populations and the carried row at
+// once. Wave 0 first collides the band's halo cells (one batch, whatever the
+// solve's halo_rows). Iteration i of the march:
+//   2. split row i's y axis: its +y and -y populations;
+//   3. finish row i - 1 (the population row i streams into it is one of them);
+//   4. issue the loads of row i + 1; split row i's x axis: +x and -x into LDS;
+//   5. barrier.
+// A row's +-x values are written in step 4 of its own iteration and read in
+// step 3 of the next, with the barrier between, and every wave has passed the
+// reads of iteration i before any writes of iteration i + 2: two LDS slots
+// suffice (three in step2d_tile_rows, which finishes a row after the barrier).
+// Per cell, every value is computed by the same expressions as in
+// step2d_tile_rows, so the results are bitwise the same.
+// ---------------------------------------------------------------------------
+template <int KIND, class T, int BASIS, int W>
+__device__ inline void step2d_tile_axes(const SolveDesc& sd, int tile) {
+  using K = Kern<KIND, 2, T, BASIS>;
+  static_assert(K::DELTA, "the axis-split march needs U stored in the rest slot");
+  constexpr int P = K::P, Q = 5, REST = 2;
+  __shared__ double red[2 * (W / 64) + 2], red_end[2 * (W / 64) + 2];
+  const int nx = sd.nx, ny = sd.ny, H = sd.band;
+  const int nsx = (nx + W - 1) / W;
+  const int sx = tile % nsx, sy = tile / nsx;
+  const int x0 = sx * W, y0 = sy * H, y1 = min(y0 + H, ny), nr = y1 - y0;
+  const int tid = threadIdx.x;
+  const int x = x0 + tid;
+  const int xl = map_index(x < nx + 1 ? x : nx, nx, sd.bcx);
+  // bands march up (even sy) or down (odd sy), as in step2d_tile_rows
+  const bool down = (sy & 1) != 0;
+  auto row_of = [&](int i) { return down ? y1 - 1 - i : y0 + i; };
+  const StateIn in = read_state(sd);
+  const int bp = predicted_parity(sd);
+  const T* __restrict__ src = (const T*)(bp ? sd.fb : sd.fa);
+  const long long below = (long long)map_index(y0 - 1, ny, sd.bcy) * nx + xl;
+  const long long above = (long long)map_index(y1, ny, sd.bcy) * nx + xl;
+  const long long pre = down ? above : below, post = down ? below : above;
+  const int qpre = down ? 4 : 3, qpost = down ? 3 : 4;
+  // the row before the band (U and its population into the first row); the
+  // stored values of row i (r*) and of row i + 1 (n*), which are loaded
+  // while row i's x axis is split, so their memory latency overlaps that work
+  T preU[P], preq[P], rU[P], rlo[P], ry3[P], ry4[P], rx0[P], rx1[P];
+  T nU[P], nlo[P], ny3[P], ny4[P], nx0[P], nx1[P];
+  auto load_next = [&](int i) {
+    const long long cell = (long long)row_of(i) * nx + xl;
+    K::load_slot_stream(src, cell, REST, nU);
+    if (K::COMP) K::load_slot_stream(src, cell, Q, nlo);
+    K::load_slot_stream(src, cell, 3, ny3);
+    K::load_slot_stream(src, cell, 4, ny4);
+    K::load_slot_stream(src, cell, 0, nx0);
+    K::load_slot_stream(src, cell, 1, nx1);
+  };
+  auto take_next = [&]() {
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+      rU[v] = nU[v];
+      rlo[v] = K::COMP ? nlo[v] : T(0);
+      ry3[v] = ny3[v];
+      ry4[v] = ny4[v];
+      rx0[v] = nx0[v];
+      rx1[v] = nx1[v];
+    }
+  };
+  auto load_first = [&]() {
+    K::load_one(src, pre, qpre, preU, preq);
+    load_next(0);
+    take_next();
+  };
+  load_first();
+  double pa, pb;
+  load_partials<true>(sd, W, pa, pb);
+  const Step S = begin_step<true>(sd, red, W, in, pa, pb);
+  if (S.done) {
+    carry_done(sd, S, tile);
+    return;
+  }
+  const long long n = S.n;
+  if (int(n & 1) != bp) {
+    src = (const T*)((n & 1) ? sd.fb : sd.fa);
+    load_first();
+  }
+  T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
+  const double ixi = 1.0 / S.xi, Lam = S.lam, ch = S.ch;
+
+  constexpr int HMAX = 64;            // band rows (vklb_options.band_rows <= 64 here)
+  __shared__ T s_ex[2][2][P][W];      // row parity, (+x, -x), var, lane
+  __shared__ T s_halo[2][HMAX][P];    // (left +x, right -x), march index, var
+
+  // 1. the band's halo cells: lanes 0-31 the left column, 32-63 the right,
+  // 32 rows at a time (read after the first iteration's barrier)
+  if (tid < 64) {
+    const int side = tid >> 5;
+    const int hx = map_index(side == 0 ? x0 - 1 : x0 + W, nx, sd.bcx);
+    for (int k = tid & 31; k < nr; k += 32) {
+      T hU[P], hq[P], hs[P];
+      K::load_one(src, (long long)row_of(k) * nx + hx, side, hU, hq);
+      K::template relax_one<0>(hU, hq, side == 0, sd.ph, ixi, Lam, ch, hs);
+#pragma unroll
+      for (int v = 0; v < P; ++v) s_halo[side][k][v] = hs[v];
+    }
+  }
+  // the population the row before the band streams into the first row; then
+  // that of the row before the one being finished
+  T prevm[P];
+  K::template relax_one<1>(preU, preq, !down, sd.ph, ixi, Lam, ch, prevm);
+  // the row being finished: its U, low part and its own y populations
+  T c_rest[P], c_lo[P], c4[P], c5[P];
+  double lam = 0.0, cfm = 0.0;
+
+  // Finish the row of march index j (its +-x values are in LDS slot j & 1);
+  // ym: the population the row after it streams into it.
+  auto finish = [&](int j, const T (&ym)[P]) {
+    const int rr = row_of(j);
+    const int ps = j & 1;
+    const long long cell = (long long)rr * nx + x;
+    T Un[P];
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+      const T a1 = tid > 0 ? s_ex[ps][0][v][tid - 1] : s_halo[0][j][v];
+      const T a2 = tid < W - 1 ? s_ex[ps][1][v][tid + 1] : s_halo[1][j][v];
+      const T a4 = down ? ym[v] : prevm[v];
+      const T a5 = down ? prevm[v] : ym[v];
+      __builtin_nontemporal_store(a1, &dst[K::pidx(0 * P + v, cell)]);
+      __builtin_nontemporal_store(a2, &dst[K::pidx(1 * P + v, cell)]);
+      __builtin_nontemporal_store(a4, &dst[K::pidx(3 * P + v, cell)]);
+      __builtin_nontemporal_store(a5, &dst[K::pidx(4 * P + v, cell)]);
+      const T b1 = s_ex[ps][0][v][tid], b2 = s_ex[ps][1][v][tid];
+      T lo_new;
+      Un[v] = K::advance(c_rest[v], ((a1 - b1) + (a2 - b2)) + ((a4 - c4[v]) + (a5 - c5[v])), c_lo[v], lo_new);
+      if (K::COMP) __builtin_nontemporal_store(lo_new, &dst[K::pidx(Q * P + v, cell)]);
+      __builtin_nontemporal_store(Un[v], &dst[K::pidx(REST * P + v, cell)]);
+    }
+    K::new_state(sd, Un, cell, n + 1, lam, cfm);
+  };
+
+  for (int i = 0; i < nr; ++i) {
+    // 2. row i's y split (row i came with the previous iteration, row 0 at entry)
+    if (i > 0) take_next();
+    T fs3[P], fs4[P];
+    K::template relax_axis<1>(rU, ry3, ry4, sd.ph, ixi, Lam, ch, fs3, fs4);
+    // 3. finish the row before
+    if (i > 0) {
+      if (x < nx) finish(i - 1, down ? fs3 : fs4);
+#pragma unroll
+      for (int v = 0; v < P; ++v) prevm[v] = down ? c5[v] : c4[v];
+    }
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+      c_rest[v] = rU[v];
+      c_lo[v] = K::COMP ? rlo[v] : T(0);
+      c4[v] = fs3[v];
+      c5[v] = fs4[v];
+    }
+    // 4. load row i + 1; row i's x split, into LDS
+    {
+      T fs0[P], fs1[P];
+      if (i + 1 < nr) load_next(i + 1);
+      K::template relax_axis<0>(rU, rx0, rx1, sd.ph, ixi, Lam, ch, fs0, fs1);
+      const int slot = i & 1;
+#pragma unroll
+      for (int v = 0; v < P; ++v) { s_ex[slot][0][v][tid] = fs0[v]; s_ex[slot][1][v][tid] = fs1[v]; }
+    }
+    // 5.
+    __syncthreads();
+  }
+  // The row after the band in march order: only the population it streams
+  // into the last row is used; it finishes that row.
+  {
+    T postU[P], postq[P], ym[P];
+    K::load_one(src, post, qpost, postU, postq);
+    K::template relax_one<1>(postU, postq, down, sd.ph, ixi, Lam, ch, ym);
+    if (x < nx) finish(nr - 1, ym);
+  }
+  block_max2<true>(lam, cfm, red_end, W);
+  end_step(sd, S, tile, lam, cfm);
+}
+
+// 2D step of one tile: the axis-split march for MHD in the delta bases,
+// else the row march.
+template <int KIND, class T, int BASIS, int W>
+__device__ inline void step2d_tile(const SolveDesc& sd, int tile) {
+  if constexpr (KIND == K_MHD && BASIS >= 1) step2d_tile_axes<KIND, T, BASIS, W>(sd, tile);
+  else step2d_tile_rows<KIND, T, BASIS, W>(sd, tile);
 }
 
 template <int KIND, class T, int BASIS, int W>

@@ -7,6 +7,12 @@
 // requests are not starved by later small ones.
 // Execution: a round is one batched launch per system class over the work
 // list of (solve slot, tile) items of every resident solve of that class.
+// While a class's resident set stays the same from one vklb_pool_run to the
+// next, its chunk of rounds is captured once into a HIP graph and replayed;
+// an admission or completion in the class drops its graph.
+// Tile shapes: 1D tiles are 256 lanes; 2D strips are 128 columns, with band
+// and halo heights per (system, size class) from vklb_pool_autotune when it
+// was called in the process, else the single-solve defaults.
 // All resident solves share the round parity; a solve admitted before round
 // r is initialized into parity r & 1. A class's round depends only on that
 // class's previous round, so each class runs on a stream of its own and small
@@ -20,8 +26,10 @@
 #include <time.h>
 
 #include <algorithm>
+#include <array>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -102,6 +110,7 @@ struct Req {
   Layout L;
   int cls = 0;
   int band = 32;
+  int halo = 32;
   size_t off = 0;
   SolveDesc sd;
   int slot = -1;
@@ -167,7 +176,15 @@ struct vklb_pool {
   SlotStatus* d_status = nullptr;
   SlotStatus* h_status = nullptr;   // pinned
   long long round = 0;
-  bool dirty = true;
+  bool dirty = true;                // work lists need uploading
+  bool changed[kClasses] = {};      // the class's resident set changed since its last rounds
+  hipGraph_t graph[kClasses] = {};  // the class's captured chunk of rounds (stable resident set)
+  hipGraphExec_t gexec[kClasses] = {};
+  int graph_rounds[kClasses] = {};
+  int graph_par[kClasses] = {};
+  int stable_calls[kClasses] = {};  // consecutive vklb_pool_run calls with an unchanged resident set
+  long long graph_launches = 0, graph_captures = 0;
+
   std::deque<vklb_completion> done;
   vklb_pool_stats stats;
   std::string err;
@@ -185,6 +202,41 @@ vklb_status pfail(vklb_pool* p, vklb_status st, const std::string& m) {
     hipError_t e_ = (call);                                                                   \
     if (e_ != hipSuccess) return pfail((p), VKLB_ERR_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
   } while (0)
+
+// Half-octave size class of a 2D grid side: round(2 log2 n).
+int size_class(long long n) { return int(lround(2.0 * log2(double(n > 0 ? n : 1)))); }
+
+// Tuned 2D shapes, kept for the process: (device, precision, kind, size
+// class) -> (band, halo).
+std::mutex g_tiles_mu;
+std::map<std::array<int, 4>, std::pair<int, int>> g_tiles;
+
+// Band and halo heights for a 2D solve of this kind and side: the tuned entry
+// of its size class, else the nearest tuned class of the kind, else the
+// single-solve defaults.
+void pick_shape(const vklb_pool* p, int kind, long long n, int* band, int* halo) {
+  *band = default_band(kind);
+  *halo = default_halo(kind);
+  const int want = size_class(n);
+  int bestd = 1 << 30;
+  std::lock_guard<std::mutex> lk(g_tiles_mu);
+  for (const auto& kv : g_tiles) {
+    if (kv.first[0] != p->device || kv.first[1] != int(p->prec) || kv.first[2] != kind) continue;
+    const int d = abs(kv.first[3] - want);
+    if (d < bestd) {
+      bestd = d;
+      *band = kv.second.first;
+      *halo = kv.second.second;
+    }
+  }
+}
+
+void drop_class_graph(vklb_pool* p, int c) {
+  if (p->gexec[c]) (void)hipGraphExecDestroy(p->gexec[c]);
+  if (p->graph[c]) (void)hipGraphDestroy(p->graph[c]);
+  p->gexec[c] = nullptr;
+  p->graph[c] = nullptr;
+}
 
 vklb_status admit(vklb_pool* p) {
   std::vector<Req*> admitted;
@@ -204,7 +256,7 @@ vklb_status admit(vklb_pool* p) {
     p->slots[slot] = r;
     const int width = r->grid.dim == 1 ? 256 : 128;  // the batched kernels' tile widths
     r->sd = make_desc(p->base + off, r->L, &r->sys, &r->grid, &r->speed, r->omega, r->bc, &r->eq, width, r->band,
-                      default_halo(r->sys.kind));
+                      r->halo);
     r->sd.npar = int(p->round & 1);  // step 0 runs at the parity of the next round
     if (r->sd.nblocks > kFoldAbove) r->sd.nred = 1;  // as a single solve: partials folded after each round
     // initialization into the parity of the next round
@@ -226,6 +278,7 @@ vklb_status admit(vklb_pool* p) {
     PCHK(p, launch_fold(d, d.par, p->stream));
     PCHK(p, K.init_feq(d, grid_for_cells(cells), p->stream));
     p->dirty = true;
+    p->changed[r->cls] = true;
     p->stats.admitted++;
   }
   if (!admitted.empty()) {
@@ -348,6 +401,9 @@ vklb_status vklb_pool_submit(vklb_pool* p, const vklb_request* rq, uint64_t* tic
   r->U_out = rq->U_out;
   r->cls = class_of(r->sys.kind, r->grid.dim);
   r->band = default_band(r->sys.kind);
+  r->halo = default_halo(r->sys.kind);
+  if (r->grid.dim == 2) pick_shape(p, r->sys.kind, r->grid.n[0], &r->band, &r->halo);
+  r->band = std::min(r->band, max_band(r->sys.kind, r->grid.dim, p->basis[r->grid.dim]));
   p->queue.push_back(r);
   p->stats.submitted++;
   if (ticket) *ticket = r->ticket;
@@ -364,20 +420,61 @@ vklb_status vklb_pool_run(vklb_pool* p, int rounds) {
   if (rounds == 0) return VKLB_OK;
   // class streams start after the caller's stream (admission, lists) ...
   PCHK(p, hipEventRecord(p->ev_main, p->stream));
+  const int par0 = int(p->round & 1);
   for (int c = 0; c < kClasses; ++c) {
+    if (p->changed[c]) {
+      drop_class_graph(p, c);
+      p->stable_calls[c] = 0;
+    } else {
+      p->stable_calls[c]++;
+    }
+    p->changed[c] = false;
     if (!p->nwork[c]) continue;
-    PCHK(p, hipStreamWaitEvent(p->cls_stream[c], p->ev_main, 0));
-    std::vector<const SolveDesc*> fold;  // this class's solves whose partials are folded
-    for (int i = 0; i < kMaxSlots; ++i)
-      if (p->slots[i] && p->slots[i]->cls == c && p->slots[i]->sd.nred != p->slots[i]->sd.nblocks)
-        fold.push_back(&p->slots[i]->sd);
-    for (int k = 0; k < rounds; ++k) {
-      const int par = int((p->round + k) & 1);
-      PCHK(p, p->cls_launch[c].batched(p->d_descs, p->d_work[c], p->d_nwork + c, par, p->nwork[c], p->cls_stream[c]));
-      for (const SolveDesc* d : fold) PCHK(p, launch_fold(*d, par ^ 1, p->cls_stream[c]));
+    hipStream_t cs = p->cls_stream[c];
+    PCHK(p, hipStreamWaitEvent(cs, p->ev_main, 0));
+    if (p->gexec[c] && (p->graph_rounds[c] != rounds || p->graph_par[c] != par0)) drop_class_graph(p, c);
+    // a class whose resident set was the same at the previous call is captured
+    // once (this call) and replayed while it stays the same
+    const bool capture = !p->gexec[c] && p->stable_calls[c] >= 1;
+    if (capture) {
+      PCHK(p, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    }
+    if (!p->gexec[c]) {
+      std::vector<const SolveDesc*> fold;  // this class's solves whose partials are folded
+      for (int i = 0; i < kMaxSlots; ++i)
+        if (p->slots[i] && p->slots[i]->cls == c && p->slots[i]->sd.nred != p->slots[i]->sd.nblocks)
+          fold.push_back(&p->slots[i]->sd);
+      hipError_t e = hipSuccess;
+      for (int k = 0; k < rounds && e == hipSuccess; ++k) {
+        const int par = (par0 + k) & 1;
+        e = p->cls_launch[c].batched(p->d_descs, p->d_work[c], p->d_nwork + c, par, p->nwork[c], cs);
+        for (const SolveDesc* d : fold)
+          if (e == hipSuccess) e = launch_fold(*d, par ^ 1, cs);
+      }
+      if (capture) {
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = ee;
+        if (e == hipSuccess) e = hipGraphInstantiate(&p->gexec[c], g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          p->gexec[c] = nullptr;
+          return pfail(p, VKLB_ERR_DEVICE, std::string("capture of a round chunk: ") + hipGetErrorString(e));
+        }
+        p->graph[c] = g;
+        p->graph_rounds[c] = rounds;
+        p->graph_par[c] = par0;
+        p->graph_captures++;
+      } else if (e != hipSuccess) {
+        return pfail(p, VKLB_ERR_DEVICE, std::string("batched launch: ") + hipGetErrorString(e));
+      }
+    }
+    if (p->gexec[c]) {
+      PCHK(p, hipGraphLaunch(p->gexec[c], cs));
+      p->graph_launches++;
     }
     // ... and the caller's stream continues after every class's rounds
-    PCHK(p, hipEventRecord(p->ev_cls[c], p->cls_stream[c]));
+    PCHK(p, hipEventRecord(p->ev_cls[c], cs));
     PCHK(p, hipStreamWaitEvent(p->stream, p->ev_cls[c], 0));
   }
   p->round += rounds;
@@ -429,6 +526,7 @@ vklb_status vklb_pool_poll(vklb_pool* p, vklb_completion* out, int max, int* n) 
       p->done.push_back(c);
       p->arena.release(r->off, r->L.total);
       p->slots[live[k]] = nullptr;
+      p->changed[r->cls] = true;
       delete r;
       p->dirty = true;
       p->stats.completed++;
@@ -453,6 +551,41 @@ vklb_status vklb_pool_get_stats(const vklb_pool* p, vklb_pool_stats* st) {
   st->resident = res;
   st->arena_used = p->arena.used();
   st->arena_peak = p->arena.peak();
+  st->graph_launches = p->graph_launches;
+  st->graph_captures = p->graph_captures;
+  return VKLB_OK;
+}
+
+vklb_status vklb_pool_autotune(vklb_pool* p, const vklb_request* samples, int n, int steps, vklb_pool_tile* out,
+                               int* n_out) {
+  if (!p || (n > 0 && !samples) || n < 0 || steps < 1 || steps > 100000) return VKLB_ERR_ARG;
+  if (!p->queue.empty()) return pfail(p, VKLB_ERR_STATE, "vklb_pool_autotune: requests are queued");
+  for (Req* r : p->slots)
+    if (r) return pfail(p, VKLB_ERR_STATE, "vklb_pool_autotune: solves are resident");
+  PCHK(p, hipSetDevice(p->device));
+  int written = 0;
+  for (int i = 0; i < n; ++i) {
+    const vklb_request& r = samples[i];
+    if (r.grid.dim != 2) continue;  // 1D tiles have one shape in the batched kernel
+    int band = 0, halo = 0;
+    double us = 0.0;
+    vklb_status st = tune_pool_shape(&r, p->prec, steps, p->stream, &band, &halo, &us);
+    if (st != VKLB_OK) return pfail(p, st, std::string("vklb_pool_autotune: ") + vklb_last_error(nullptr));
+    {
+      std::lock_guard<std::mutex> lk(g_tiles_mu);
+      g_tiles[{p->device, int(p->prec), int(r.sys.kind), size_class(r.grid.n[0])}] = {band, halo};
+    }
+    if (out && n_out && written < *n_out) {
+      vklb_pool_tile& t = out[written++];
+      t.kind = r.sys.kind;
+      t.n = r.grid.n[0];
+      t.size_class = size_class(r.grid.n[0]);
+      t.band_rows = band;
+      t.halo_rows = halo;
+      t.step_us = us;
+    }
+  }
+  if (n_out) *n_out = written;
   return VKLB_OK;
 }
 
@@ -463,6 +596,7 @@ void vklb_pool_destroy(vklb_pool* p) {
   else (void)hipDeviceSynchronize();
   for (Req* r : p->queue) delete r;
   for (Req* r : p->slots) delete r;
+  for (int c = 0; c < kClasses; ++c) drop_class_graph(p, c);
   for (int c = 0; c < kClasses; ++c) {
     if (p->cls_stream[c]) {
       (void)hipStreamSynchronize(p->cls_stream[c]);

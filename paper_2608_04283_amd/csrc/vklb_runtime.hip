@@ -130,6 +130,35 @@ __global__ void k_static_info(const DevState* st, int par, vklb_run_info* out) {
   out->done = (S.done || S.n >= st->max_steps || !(S.t < st->T) || err) ? 1 : 0;
 }
 
+// Streaming copy of n16 16-byte words: each workgroup copies one contiguous
+// chunk, 4 KiB per wavefront row of loads and four rows in flight per lane
+// before their stores (the step kernels' pattern: each workgroup reads and
+// writes its own contiguous runs once). NT: non-temporal loads and stores
+// (the step kernels' population stores and 2D row loads), else plain ones.
+typedef float v4f __attribute__((ext_vector_type(4)));
+template <bool NT>
+__global__ void __launch_bounds__(256) k_stream_copy(const v4f* __restrict__ src, v4f* __restrict__ dst,
+                                                     long long n16, long long chunk) {
+  const long long begin = (long long)blockIdx.x * chunk;
+  const long long end = begin + chunk < n16 ? begin + chunk : n16;
+  for (long long base = begin; base < end; base += 4 * 256) {
+    v4f v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long i = base + u * 256 + threadIdx.x;
+      if (i < end) v[u] = NT ? __builtin_nontemporal_load(src + i) : src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long i = base + u * 256 + threadIdx.x;
+      if (i < end) {
+        if (NT) __builtin_nontemporal_store(v[u], dst + i);
+        else dst[i] = v[u];
+      }
+    }
+  }
+}
+
 }  // namespace
 
 // Trailer of a checkpoint blob (see vklb_state_bytes).
@@ -393,7 +422,7 @@ vklb_status plan_solve(const vklb_system* sys, vklb_lattice lat, const vklb_grid
   pl->K = pick_launchers(sys->kind, grid->dim, prec == VKLB_FP32 ? 1 : 0, pl->basis, width);
   int band = o.band_rows;
   if (band < 1) band = default_band(sys->kind);
-  if (band > 4096) band = 4096;
+  if (band > max_band(sys->kind, grid->dim, pl->basis)) band = max_band(sys->kind, grid->dim, pl->basis);
   pl->band = band;
   int halo = o.halo_rows;
   if (halo < 1 || halo > 32) halo = default_halo(sys->kind);
@@ -724,20 +753,39 @@ vklb_status vklb_set_state(vklb_solver* s, const void* host) {
   return VKLB_OK;
 }
 
-vklb_status vklb_tune(const vklb_system* sys, vklb_lattice lat, const vklb_grid* grid, const vklb_speed* lambda,
-                      double omega, const vklb_bc bc[2], const vklb_equilibrium* eq, vklb_precision prec,
-                      const vklb_options* base, const double* U0_host, int steps, void* hip_stream,
-                      vklb_options* best, double* best_step_us) {
+}  // extern "C"
+
+// vklb_tune over the shapes of a single solve, or (pool_2d) over the band and
+// halo heights of the serving pool's batched 2D kernel, whose strips are 128
+// columns wide.
+static vklb_status tune_impl(const vklb_system* sys, vklb_lattice lat, const vklb_grid* grid, const vklb_speed* lambda,
+                             double omega, const vklb_bc bc[2], const vklb_equilibrium* eq, vklb_precision prec,
+                             const vklb_options* base, const double* U0_host, int steps, void* hip_stream,
+                             bool pool_2d, vklb_options* best, double* best_step_us) {
   if (!U0_host || !best || steps < 1 || steps > 100000) return fail(nullptr, VKLB_ERR_ARG, "vklb_tune: bad arguments");
   const char* msg = "";
   vklb_status vst = validate(sys, lat, grid, lambda, omega, bc, eq, prec, &msg);
   if (vst != VKLB_OK) return fail(nullptr, vst, msg);
+  if (pool_2d && grid->dim != 2) return fail(nullptr, VKLB_ERR_ARG, "vklb_tune: the pool's tuned shapes are 2D");
   vklb_options b0;
   if (base) b0 = *base;
   else memset(&b0, 0, sizeof b0);
   // candidate tile shapes
   std::vector<vklb_options> cand;
-  if (grid->dim == 1) {
+  if (pool_2d) {
+    const long long ny = grid->n[1];
+    for (int band : {4, 8, 16, 32, 64}) {
+      if (band > 4 && band / 2 >= ny) continue;
+      for (int halo : {2, 8, 16, 32}) {
+        if (halo > band) continue;
+        vklb_options o = b0;
+        o.strip_width = 128;
+        o.band_rows = band;
+        o.halo_rows = halo;
+        cand.push_back(o);
+      }
+    }
+  } else if (grid->dim == 1) {
     for (int w : {256, 512}) {
       vklb_options o = b0;
       o.strip_width = w;
@@ -802,6 +850,30 @@ vklb_status vklb_tune(const vklb_system* sys, vklb_lattice lat, const vklb_grid*
     return fail(nullptr, last != VKLB_OK ? last : VKLB_ERR_STATE, "vklb_tune: no candidate ran");
   if (best_step_us) *best_step_us = best_us;
   return VKLB_OK;
+}
+
+namespace vklb {
+vklb_status tune_pool_shape(const vklb_request* r, vklb_precision prec, int steps, void* hip_stream, int* band,
+                            int* halo, double* step_us) {
+  vklb_options best;
+  memset(&best, 0, sizeof best);
+  vklb_status st = tune_impl(&r->sys, r->lat, &r->grid, &r->lambda, r->omega, r->bc, &r->eq, prec, nullptr, r->U0,
+                             steps, hip_stream, true, &best, step_us);
+  if (st != VKLB_OK) return st;
+  *band = best.band_rows;
+  *halo = best.halo_rows;
+  return VKLB_OK;
+}
+}  // namespace vklb
+
+extern "C" {
+
+vklb_status vklb_tune(const vklb_system* sys, vklb_lattice lat, const vklb_grid* grid, const vklb_speed* lambda,
+                      double omega, const vklb_bc bc[2], const vklb_equilibrium* eq, vklb_precision prec,
+                      const vklb_options* base, const double* U0_host, int steps, void* hip_stream,
+                      vklb_options* best, double* best_step_us) {
+  return tune_impl(sys, lat, grid, lambda, omega, bc, eq, prec, base, U0_host, steps, hip_stream, false, best,
+                   best_step_us);
 }
 
 void vklb_destroy(vklb_solver* s) {
@@ -913,6 +985,35 @@ vklb_status vklb_run_static(const vklb_system* sys, vklb_lattice lat, const vklb
   if (e != hipSuccess) {
     char m[200];
     snprintf(m, sizeof m, "vklb_run_static: launch failed: %s", hipGetErrorString(e));
+    set_create_error(m);
+    return VKLB_ERR_DEVICE;
+  }
+  return VKLB_OK;
+}
+
+vklb_status vklb_stream_copy(void* dst, const void* src, size_t bytes, int non_temporal, void* hip_stream) {
+  if (!dst || !src || bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16) {
+    set_create_error("vklb_stream_copy: NULL pointer, or size or address not a multiple of 16 bytes");
+    return VKLB_ERR_ARG;
+  }
+  const long long n16 = (long long)(bytes / 16);
+  if (n16 == 0) return VKLB_OK;
+  // up to 8 workgroups of 256 lanes per compute unit, each a contiguous
+  // chunk of whole 1024-word rows of four loads per lane
+  const long long rows = (n16 + 1023) / 1024;
+  const int grid = int(std::min<long long>(2048, rows));
+  const long long chunk = (rows + grid - 1) / grid * 1024;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  if (non_temporal)
+    hipLaunchKernelGGL(k_stream_copy<true>, dim3(grid), dim3(256), 0, st, static_cast<const v4f*>(src),
+                       static_cast<v4f*>(dst), n16, chunk);
+  else
+    hipLaunchKernelGGL(k_stream_copy<false>, dim3(grid), dim3(256), 0, st, static_cast<const v4f*>(src),
+                       static_cast<v4f*>(dst), n16, chunk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    char m[160];
+    snprintf(m, sizeof m, "vklb_stream_copy: launch failed: %s", hipGetErrorString(e));
     set_create_error(m);
     return VKLB_ERR_DEVICE;
   }

@@ -4,9 +4,14 @@ Batched serving: requests are submitted to the pool at their arrival times;
 between chunks of rounds the pool admits what fits in its HBM arena (the
 others wait in order), advances every resident solve, and hands back the
 finished ones. Latency = completion time - arrival time, on the host clock.
+The pool's 2D tile shapes come from tune_shapes when it ran in the process.
 
-Plain baseline: the same kernels, one solve at a time in arrival order, one
-launch per time step (no batching, no graphs).
+Plain baseline: the single-solve path, one solve at a time in arrival order
+(the same kernels, launched as vklb_step launches them: in captured graphs of
+512 steps).
+
+Both report every completed request (solves) and, apart, those that ended in
+a non-physical state; solves_per_s counts the served (physical) solves only.
 """
 from __future__ import annotations
 
@@ -53,8 +58,27 @@ class _Prefetch:
         self.ex.shutdown(wait=False, cancel_futures=True)
 
 
-def run_batched(requests, budget_bytes, precision="fp32", chunk_rounds=32, realtime=True, keep_results=False):
-    """Serve `requests` (inputs.Request, sorted by arrival) through a pool."""
+TUNE_SIZES = (128, 181, 256, 362, 512, 724, 1024)
+
+
+def tune_shapes(precision="fp32", steps=20, seed=11, sizes=TUNE_SIZES):
+    """Tune the pool's batched 2D tile shapes (vklb_pool_autotune) on one
+    two-state request per system and half-octave grid size of the request
+    stream's 2D range; the library keeps the table for the process, so every
+    pool created afterwards uses it. Returns the table."""
+    samples = [inputs.random_riemann(system, 2, n, seed=seed * 100 + i * 10 + k, max_steps=steps)
+               for i, system in enumerate(("sw", "euler", "mhd")) for k, n in enumerate(sizes)]
+    pool = vklb.Pool(1 << 24, precision)
+    try:
+        return pool.autotune(samples, steps=steps)
+    finally:
+        pool.close()
+
+
+def run_batched(requests, budget_bytes, precision="fp32", chunk_rounds=32, realtime=True, keep_results=False,
+                progress=None):
+    """Serve `requests` (inputs.Request, sorted by arrival) through a pool;
+    progress(done, total) is called after every 200th completion."""
     reqs = sorted(requests, key=lambda r: r.arrival)
     pool = vklb.Pool(budget_bytes, precision)
     pre = _Prefetch(reqs)
@@ -85,6 +109,8 @@ def run_batched(requests, budget_bytes, precision="fp32", chunk_rounds=32, realt
                 latencies.append(t_done - arrival[c["tag"]])
                 cell_steps += c["problem"].cells * c["steps"]
                 n_done += 1
+                if progress and n_done % 200 == 0:
+                    progress(n_done, len(reqs))
                 if c["status"] != 0:
                     failed.append((c["tag"], c["problem"].name, c["fail_step"], c["fail_cell"]))
                 if keep_results:
@@ -95,15 +121,20 @@ def run_batched(requests, budget_bytes, precision="fp32", chunk_rounds=32, realt
         pre.close()
         pool.close()
     p50, p99 = _percentiles(latencies)
-    return {"mode": "batched", "solves": n_done, "makespan_s": makespan, "solves_per_s": n_done / makespan,
+    ok = n_done - len(failed)
+    return {"mode": "batched", "solves": n_done, "ok": ok, "makespan_s": makespan, "solves_per_s": ok / makespan,
+            "completed_per_s": n_done / makespan,
             "p50_s": p50, "p99_s": p99, "cell_steps": cell_steps, "mcell_steps_per_s": cell_steps / makespan / 1e6,
             "nonphysical": len(failed), "failed": failed, "arena_peak_bytes": stats["arena_peak"],
-            "rounds": stats["rounds"],
+            "rounds": stats["rounds"], "graph_launches": stats["graph_launches"],
+            "graph_captures": stats["graph_captures"],
             "results": results if keep_results else None}
 
 
-def run_plain(requests, precision="fp32", realtime=True, keep_results=False):
-    """One solve at a time in arrival order, one kernel launch per time step."""
+def run_plain(requests, precision="fp32", realtime=True, keep_results=False, graph_chunk=0, progress=None):
+    """One solve at a time in arrival order through the single-solve path
+    (graph_chunk 0: its default graph chunks; -1: one plain launch per step);
+    progress(done, total) is called after every 100th solve."""
     reqs = sorted(requests, key=lambda r: r.arrival)
     pre = _Prefetch(reqs)
     latencies = []
@@ -117,7 +148,7 @@ def run_plain(requests, precision="fp32", realtime=True, keep_results=False):
             now = time.perf_counter() - t0
             if realtime and rq.arrival > now:
                 time.sleep(rq.arrival - now)
-            s = vklb.Solver(prob, precision=precision, graph_chunk=-1)
+            s = vklb.Solver(prob, precision=precision, graph_chunk=graph_chunk)
             s.init()
             try:
                 U, t, n = s.run()
@@ -133,13 +164,17 @@ def run_plain(requests, precision="fp32", realtime=True, keep_results=False):
             t_done = time.perf_counter() - t0
             latencies.append(t_done - (rq.arrival if realtime else 0.0))
             cell_steps += prob.cells * n
+            if progress and len(latencies) % 100 == 0:
+                progress(len(latencies), len(reqs))
             if keep_results:
                 results[rq.rid] = (U, t, n, status)
         makespan = time.perf_counter() - t0
     finally:
         pre.close()
     p50, p99 = _percentiles(latencies)
-    return {"mode": "plain", "solves": len(reqs), "makespan_s": makespan, "solves_per_s": len(reqs) / makespan,
+    ok = len(reqs) - len(failed)
+    return {"mode": "plain", "solves": len(reqs), "ok": ok, "makespan_s": makespan, "solves_per_s": ok / makespan,
+            "completed_per_s": len(reqs) / makespan,
             "p50_s": p50, "p99_s": p99, "cell_steps": cell_steps, "mcell_steps_per_s": cell_steps / makespan / 1e6,
             "nonphysical": len(failed), "failed": failed, "results": results if keep_results else None}
 

@@ -26,7 +26,7 @@ EXPORTED = ["vklb_workspace_bytes", "vklb_create", "vklb_set_end", "vklb_init", 
             "vklb_progress", "vklb_diagnostics", "vklb_state_bytes", "vklb_get_state", "vklb_set_state", "vklb_last_step_ms",
             "vklb_destroy", "vklb_status_str", "vklb_last_error", "vklb_pool_create", "vklb_pool_submit",
             "vklb_pool_run", "vklb_pool_poll", "vklb_pool_get_stats", "vklb_pool_destroy", "vklb_tune",
-            "vklb_run_static"]
+            "vklb_run_static", "vklb_stream_copy", "vklb_pool_autotune"]
 STATIC_BYTES = 64 * 1024 * 1024  # VKLB_STATIC_BYTES
 
 
@@ -86,7 +86,13 @@ class RunInfo(ctypes.Structure):
 class PoolStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("resident", ctypes.c_int64), ("rounds", ctypes.c_int64),
-                ("arena_bytes", ctypes.c_size_t), ("arena_used", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t)]
+                ("arena_bytes", ctypes.c_size_t), ("arena_used", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t),
+                ("graph_launches", ctypes.c_int64), ("graph_captures", ctypes.c_int64)]
+
+
+class PoolTile(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("n", ctypes.c_int64), ("size_class", ctypes.c_int), ("band_rows", ctypes.c_int),
+                ("halo_rows", ctypes.c_int), ("step_us", ctypes.c_double)]
 
 
 _lib = None
@@ -136,6 +142,9 @@ def lib():
     L.vklb_pool_run.argtypes = [vp, ctypes.c_int]
     L.vklb_pool_poll.argtypes = [vp, ctypes.POINTER(Completion), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     L.vklb_pool_get_stats.argtypes = [vp, ctypes.POINTER(PoolStats)]
+    L.vklb_pool_autotune.argtypes = [vp, ctypes.POINTER(Request), ctypes.c_int, ctypes.c_int, ctypes.POINTER(PoolTile),
+                                     ctypes.POINTER(ctypes.c_int)]
+    L.vklb_pool_autotune.restype = ctypes.c_int
     L.vklb_pool_destroy.argtypes = [vp]
     L.vklb_pool_destroy.restype = None
     L.vklb_tune.argtypes = [ctypes.POINTER(System), ctypes.c_int, ctypes.POINTER(Grid), ctypes.POINTER(Speed),
@@ -145,6 +154,8 @@ def lib():
                                   ctypes.c_double, ctypes.c_int * 2, ctypes.POINTER(Equilibrium), ctypes.c_int,
                                   ctypes.c_double, ctypes.c_int64, vp, vp, vp, vp]
     L.vklb_run_static.restype = ctypes.c_int
+    L.vklb_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int, vp]
+    L.vklb_stream_copy.restype = ctypes.c_int
     for name in ("vklb_pool_create", "vklb_pool_submit", "vklb_pool_run", "vklb_pool_poll", "vklb_pool_get_stats"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("vklb_create", "vklb_set_end", "vklb_init", "vklb_init_device", "vklb_step", "vklb_moments", "vklb_progress",
@@ -217,6 +228,40 @@ def run_static(problem, precision, n_steps, U0_dev_ptr, U_dev_ptr, info_dev_ptr=
                           ctypes.c_void_p(int(info_dev_ptr)) if info_dev_ptr else None, ctypes.c_void_p(sptr))
     if r != OK:
         raise VklbError(r, L.vklb_last_error(None).decode())
+
+
+def stream_copy(dst_ptr, src_ptr, nbytes, non_temporal=True, stream=None):
+    """vklb_stream_copy: the library's streaming copy kernel (device pointers)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    r = lib().vklb_stream_copy(ctypes.c_void_p(int(dst_ptr)), ctypes.c_void_p(int(src_ptr)), int(nbytes),
+                               1 if non_temporal else 0, ctypes.c_void_p(st.cuda_stream))
+    if r != OK:
+        raise VklbError(r, lib().vklb_last_error(None).decode())
+
+
+def stream_copy_bench(nbytes, reps=5):
+    """Copy ceiling: HIP-event time of `reps` streaming copies of nbytes
+    (after one warm-up) in both load/store forms; GB/s counts the bytes read
+    plus the bytes written."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    out = {"bytes_per_copy": nbytes, "reps": reps}
+    for nt in (True, False):
+        stream_copy(b.data_ptr(), a.data_ptr(), nbytes, nt, st)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            stream_copy(b.data_ptr(), a.data_ptr(), nbytes, nt, st)
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out["non_temporal" if nt else "plain"] = {"ms_per_copy": round(ms, 4),
+                                                  "gb_per_s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+    del a, b
+    return out
 
 
 class Solver:
@@ -376,6 +421,30 @@ class Pool:
             raise VklbError(r, "vklb_pool_create failed")
         self._h = h
         self._live = {}   # ticket -> (problem, U0, U_out)
+
+    def _request(self, problem, U0, Uo, tag):
+        sysd, lat, grid, speed, eq, bc = _structs(problem)
+        T = problem.T if problem.T is not None else math.inf
+        ms = int(problem.max_steps) if problem.max_steps < 2**62 else -1
+        return Request(sysd, lat, grid, speed, float(problem.omega), bc, eq, float(T), ms,
+                       U0.ctypes.data_as(ctypes.c_void_p), Uo.ctypes.data_as(ctypes.c_void_p), int(tag))
+
+    def autotune(self, problems, steps=20):
+        """vklb_pool_autotune over sample problems (their 2D ones); returns the
+        tuned shapes as dicts. Call before the first submit."""
+        keep = []
+        reqs = (Request * max(1, len(problems)))()
+        for i, P in enumerate(problems):
+            U0 = np.ascontiguousarray(np.asarray(P.U0, dtype=np.float64).reshape(P.p, P.cells))
+            Uo = np.empty_like(U0)
+            keep.append((U0, Uo))
+            reqs[i] = self._request(P, U0, Uo, i)
+        out = (PoolTile * max(1, len(problems)))()
+        n = ctypes.c_int(len(problems))
+        r = lib().vklb_pool_autotune(self._h, reqs, len(problems), int(steps), out, ctypes.byref(n))
+        if r != OK:
+            raise VklbError(r, "vklb_pool_autotune failed")
+        return [{f: getattr(out[i], f) for f, _ in PoolTile._fields_} for i in range(n.value)]
 
     def submit(self, problem, tag=0):
         sysd, lat, grid, speed, eq, bc = _structs(problem)
