@@ -5,15 +5,22 @@ One benchmark step = one full solve of the workload: initialization from an
 initial state already resident in HBM, then every time step to the end
 condition (collision, streaming, moments and the per-step CFL update, one
 fused HIP kernel per time step; grids of up to 1024 cells run many steps per
-launch in one workgroup). Default workload: the 1D Euler shock tube,
-N = 65,536 cells to t = 0.2, FP32 (FP64 reported beside it).
+launch in one workgroup).
+
+Headline workload: 2D Euler four-quadrant Riemann data, 2048^2 cells, 2000
+steps, FP32 populations: the largest single-GPU configuration, and the one
+whose working set (671 MB) is far above the 256 MB Infinity Cache, so its
+HBM fraction measures HBM. The other configurations run beside it under
+"also" (1D shallow water in both lattice forms, 1D Euler shock tube FP32 and
+FP64, the 1D smooth wave to 65,536 cells, 1D and 2D MHD), and the mixed
+request stream under "serving".
 
 Prints one JSON line: value = cells x time steps / second (Mcell-steps/s) of
 the timed solves; roofline = algorithmic bytes of the step kernel (each
 population read once and written once, 2 Q p s bytes per cell-step, times
 the cells and steps of a launch) over its average launch duration, measured
-with HIP events on the solver's stream;
-cpu_baseline = the FP64 oracle on a bounded sample of the same workload.
+with HIP events on the solver's stream; cpu_baseline = the FP64 oracle on a
+bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -22,27 +29,39 @@ import hashlib
 import json
 import math
 import os
+import platform
 import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-if ROOT not in sys.path:
-    sys.path.insert(0, ROOT)
+for _p in (ROOT, os.path.join(ROOT, "tests")):
+    if _p not in sys.path:
+        sys.path.insert(0, _p)
 
 from paper_2608_04283_amd import inputs as I  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 
+# name: problem factory, precisions (first = the one reported first), warm-up
+# and timed solves for a line under "also", the oracle window of its CPU
+# baseline (time steps), and the lattice it runs (D1Q2 = the weighted set
+# with c = 1/2, k = 0, whose rest population is identically zero)
 WORKLOADS = {
-    # name: (problem factory, precisions, cpu-baseline sample steps)
-    "euler1d_sod": (lambda: I.sod(65536), ("fp32", "fp64"), 3500),
-    "sw1d_dambreak": (lambda: I.dam_break(1000, c=0.5, k=0.0), ("fp64",), 600),
-    "euler2d_quadrants": (lambda: I.quadrants(2048, seed=0, steps=2000), ("fp32",), 4),
-    "mhd1d_briowu": (lambda: I.brio_wu(16384), ("fp32",), 300),
-    "mhd2d_orszag_tang": (lambda: I.orszag_tang(1024, steps=1000), ("fp32",), 2),
+    "euler2d_quadrants": (lambda: I.quadrants(2048, seed=0, steps=2000), ("fp32",), (1, 3), 20, "D2Q5"),
+    "euler1d_sod": (lambda: I.sod(65536), ("fp32", "fp64"), (1, 2), 200, "D1Q3"),
+    "euler1d_wave": (lambda: I.smooth_wave(65536), ("fp64", "fp32"), (1, 1), 200, "D1Q3"),
+    "sw1d_dambreak": (lambda: I.dam_break(1000), ("fp64",), (1, 3), None, "D1Q3"),
+    "sw1d_dambreak_d1q2": (lambda: I.dam_break(1000, c=0.5, k=0.0), ("fp64",), (1, 3), None, "D1Q2"),
+    "mhd1d_briowu": (lambda: I.brio_wu(16384), ("fp32",), (1, 2), 400, "D1Q3"),
+    "mhd2d_orszag_tang": (lambda: I.orszag_tang(1024, steps=1000), ("fp32",), (1, 3), 2, "D2Q5"),
 }
-DEFAULT = "euler1d_sod"
+HEADLINE = "euler2d_quadrants"
+
+
+def log(msg):
+    """Progress of the run, on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def alg_bytes_per_cell_step(P, prec):
@@ -65,7 +84,7 @@ def kernel_sources_sha():
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(workload, prec, cells_per_launch):
+def profiled_traffic(workload, prec):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{prec}.md")
@@ -81,25 +100,27 @@ def profiled_traffic(workload, prec, cells_per_launch):
 
 # Stored FP64 oracle results (written by tests/golden/make_oracle_goldens.py,
 # which runs the oracle alone) that each workload's final state is compared
-# with: the workload itself (1D), or the size its oracle comparison uses (2D),
-# which is then run on the GPU beside the timed solves.
+# with: the workload itself, or the size its oracle comparison uses, which is
+# then run on the GPU beside the timed solves.
 GOLDEN = {
     "euler1d_sod": ("oracle_euler1d_sod_n65536.npz", None),
-    "sw1d_dambreak": ("oracle_sw1d_dambreak_d1q2_n1000.npz", None),
+    "euler1d_wave": ("oracle_euler1d_wave_n16384.npz", lambda: I.smooth_wave(16384)),
+    "sw1d_dambreak": ("oracle_sw1d_dambreak_wu_n1000.npz", None),
+    "sw1d_dambreak_d1q2": ("oracle_sw1d_dambreak_d1q2_n1000.npz", None),
     "mhd1d_briowu": ("oracle_mhd1d_briowu_n16384.npz", None),
     "euler2d_quadrants": ("oracle_euler2d_quadrants_n512_s0.npz", lambda: I.quadrants(512, seed=0, steps=2000)),
     "mhd2d_orszag_tang": ("oracle_mhd2d_orszag_tang_n256.npz", lambda: I.orszag_tang(256, steps=1000)),
 }
 
 
-def rel_l1(a, b, small=1e-3):
-    """Per field sum|a - b| / sum|b|; fields whose L1 norm is below `small`
-    times the largest field's (identically zero ones) are measured against
-    the largest field's norm."""
+def rel_l1(a, b, zero=1e-12):
+    """Per field sum|a - b| / sum|b| (b the oracle); a field that is
+    identically zero in b (L1 norm at most `zero` times the largest field's)
+    is measured against the largest field's norm."""
     import numpy as np
     num = np.abs(a - b).sum(axis=1)
     den = np.abs(b).sum(axis=1)
-    den = np.where(den <= small * den.max(), den.max(), den)
+    den = np.where(den <= zero * den.max(), den.max(), den)
     return num / den
 
 
@@ -125,23 +146,42 @@ def error_vs_oracle(name, prec, U_final):
             "at_size": size or "the workload's", "oracle": "FP64"}
 
 
+def error_vs_exact(name, P, U, t):
+    """Mean absolute error of the first field(s) against the exact solution,
+    where one exists: the dam break (exact Riemann solution, h and hu) and
+    the smooth wave (rho(x - t), exact cell averages)."""
+    import numpy as np
+    n = P.n[0]
+    if name.startswith("sw1d_dambreak"):
+        from exact_riemann import ShallowWaterRiemann, cell_average_exact
+        ex = ShallowWaterRiemann(2.0, 0.0, 1.0, 0.0, P.g)
+        hu = cell_average_exact(lambda s: np.stack(ex.sample(s)), np.linspace(0, 1, n + 1), t, 0.5, sub=4)
+        exact = np.stack([hu[0], hu[0] * hu[1]])
+        l1 = np.abs(U - exact).mean(axis=1)
+        return {"l1_h": float(f"{l1[0]:.4g}"), "l1_hu": float(f"{l1[1]:.4g}"), "exact": "dam-break Riemann solution"}
+    if name == "euler1d_wave":
+        x = (np.arange(n) + 0.5) / n
+        dx = 1.0 / n
+        avg = 1.0 + 0.2 * (np.cos(2 * np.pi * (x - dx / 2 - t)) - np.cos(2 * np.pi * (x + dx / 2 - t))) / (2 * np.pi * dx)
+        return {"l1_rho": float(f"{np.abs(U[0] - avg).mean():.4g}"), "exact": "rho(x - t) cell averages"}
+    return None
+
+
 def step_kernel(P, steps):
     """The kernel that advances the workload and the steps one launch takes:
     1D grids of up to 1024 cells (256 for MHD) run up to 1024 steps per
-    launch in one workgroup
-    (k_run1d_wg, the library's rule for its default options); everything else
-    launches k_step1d / k_step2d once per step."""
+    launch in one workgroup (k_run1d_wg, the library's rule for its default
+    options); everything else launches k_step1d / k_step2d once per step."""
     if P.dim == 1 and P.cells <= (256 if P.system == "mhd" else 1024):
         return "k_run1d_wg", min(1024, steps)
     return f"k_step{P.dim}d", 1
 
 
-def time_workload(name, prec, K, W, quick=False):
+def time_workload(name, prec, K, W):
     import torch
     from paper_2608_04283_amd import vklb
 
-    factory, _, _ = WORKLOADS[name]
-    P = factory()
+    P = WORKLOADS[name][0]()
     s = vklb.Solver(P, precision=prec)
     U0 = torch.from_numpy(P.U0).to("cuda").contiguous()
     stream = torch.cuda.current_stream()
@@ -152,9 +192,8 @@ def time_workload(name, prec, K, W, quick=False):
         U, t, n = s.run()
         steps = n
     torch.cuda.synchronize()
-    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
     step_ms = 0.0
-    wall0 = time.perf_counter()
     e0.record(stream)
     for k in range(K):
         s.init_device(U0.data_ptr())
@@ -168,71 +207,115 @@ def time_workload(name, prec, K, W, quick=False):
         torch.cuda.synchronize()
         step_ms += a.elapsed_time(b)
     e1.synchronize()
-    wall = time.perf_counter() - wall0
     total_ms = e0.elapsed_time(e1)
     t_end, n_end, done = s.progress()
     U_final, _, _ = s.moments()
+    diag = s.diagnostics()
     s.close()
     assert n_end == steps and done, (n_end, steps, done)
     cells = P.cells
-    cell_steps = cells * steps * K
-    value = cell_steps / (total_ms * 1e-3) / 1e6
+    value = cells * steps * K / (total_ms * 1e-3) / 1e6
     step_time_ms = step_ms / (steps * K)
     kernel, spl = step_kernel(P, steps)
-    achieved = alg_bytes_per_cell_step(P, prec) * cells / (step_time_ms * 1e-3) / 1e9
-    traffic = profiled_traffic(name, prec, cells)
+    abytes = alg_bytes_per_cell_step(P, prec)
+    achieved = abytes * cells / (step_time_ms * 1e-3) / 1e9
+    two_d = P.dim == 2
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(name, prec),
             "kernel": kernel, "avg_launch_us": round(step_time_ms * spl * 1e3, 3), "steps_per_launch": spl,
-            "us_per_step": round(step_time_ms * 1e3, 3),
-            "alg_bytes_per_cell_step": alg_bytes_per_cell_step(P, prec), "cells_per_launch": cells}
-    err = error_vs_oracle(name, prec, U_final)
-    return {"workload": P.name, "value": value, "ms_per_solve": total_ms / K, "steps_per_solve": steps, "error": err,
-            "cells": cells, "t_end": t_end, "roofline": roof, "wall_s": wall, "dtype": "f32" if prec == "fp32" else "f64"}
+            "us_per_step": round(step_time_ms * 1e3, 3), "alg_bytes_per_cell_step": abytes,
+            "cells_per_launch": cells, "populations_mb": round(abytes * cells / 1e6, 1)}
+    if not two_d:
+        roof["note"] = ("working set cache-resident between steps: the step is bound by the latency of one "
+                        "dependent launch, not by HBM")
+    out = {"workload": P.name, "value": value, "ms_per_solve": total_ms / K, "steps_per_solve": steps,
+           "error": error_vs_oracle(name, prec, U_final), "exact": error_vs_exact(name, P, U_final, t_end),
+           "cells": cells, "t_end": t_end, "roofline": roof, "dtype": "f32" if prec == "fp32" else "f64",
+           "params": {"lattice": WORKLOADS[name][4], "omega": P.omega, "c": P.c, "k": P.k, "nu": P.nu,
+                      "bc": P.bc[0]}}
+    if P.system == "mhd" and two_d:
+        out["max_div_b"] = float(f"{diag['max_div_b']:.4g}")
+    log(f"{P.name} {prec}: {value:.1f} Mcell-steps/s, {step_time_ms * 1e3:.2f} us per step")
+    return out
 
 
-def serving_bench(count, seed=1, budget=None):
-    """Batched serving vs plain per-solve launches on a sample of the mixed
-    request stream (systems, sizes and step counts drawn as in
-    inputs.serving_requests). Capacity = solves/s of the batched pool with
-    every request present at once; the timed streams then arrive as a Poisson
-    process at 80 % of that capacity, once through the pool and once through
-    plain per-solve launches."""
+def serving_bench(count, seed=1, budget=None, sample_every=5):
+    """Batched serving against plain per-solve launches on the mixed request
+    stream (systems, sizes and step counts drawn as in
+    inputs.serving_requests, seed 1). Capacity = solves/s of the batched pool
+    with every request present at once; the timed stream then arrives as a
+    Poisson process at 80 % of that capacity. The plain baseline (one solve
+    at a time, the single-solve path with its 512-step graph chunks) is
+    measured closed-loop, on every `sample_every`-th request beside the pool
+    on the same sample: at the batched arrival rate it cannot keep up, so its
+    timed run would only grow its queue. Solves that turn non-physical are
+    counted apart from the served solves/s."""
     import torch
     from paper_2608_04283_amd import serving
     if budget is None:
         free, _ = torch.cuda.mem_get_info()
         budget = int(min(free * 0.6, 96 << 30)) // 256 * 256
+    t0 = time.perf_counter()
+    tiles = serving.tune_shapes("fp32")
+    tune_s = time.perf_counter() - t0
     reqs = I.serving_requests(count, seed=seed)
     cell_steps = sum(r.problem.cells * r.steps for r in reqs)
-    cap = serving.run_batched(reqs, budget, "fp32", realtime=False)
+    keep = ("solves", "ok", "nonphysical", "makespan_s", "solves_per_s", "completed_per_s", "p50_s", "p99_s",
+            "mcell_steps_per_s", "graph_launches", "graph_captures")
+    r = lambda d: {k: (round(d[k], 4) if isinstance(d[k], float) else d[k]) for k in keep if k in d}
+    log(f"serving: 2D tile shapes tuned in {tune_s:.1f} s")
+    prog = lambda what: (lambda k, n: log(f"serving {what}: {k} of {n} solves done"))
+    cap = serving.run_batched(reqs, budget, "fp32", realtime=False, progress=prog("capacity"))
     rate = 0.8 * cap["solves_per_s"]
     timed = serving.with_arrivals(reqs, rate, seed=seed + 1)
-    batched = serving.run_batched(timed, budget, "fp32", realtime=True)
-    plain_cap = serving.run_plain(reqs, "fp32", realtime=False)
-    plain = serving.run_plain(timed, "fp32", realtime=True)
-    keep = ("solves", "makespan_s", "solves_per_s", "p50_s", "p99_s", "mcell_steps_per_s", "nonphysical", "failed")
-    r = lambda d: {k: (round(d[k], 4) if isinstance(d[k], float) else d[k]) for k in keep}
+    batched = serving.run_batched(timed, budget, "fp32", realtime=True, progress=prog("at 80 %"))
+    sample = reqs[::sample_every]
+    cap_s = serving.run_batched(sample, budget, "fp32", realtime=False)
+    log("serving: batched sample done")
+    plain_s = serving.run_plain(sample, "fp32", realtime=False, progress=prog("plain sample"))
+    names = {0: "sw", 1: "euler", 2: "mhd"}
     return {"requests": count, "seed": seed, "cell_steps": cell_steps, "arena_bytes": budget,
-            "capacity_solves_per_s": round(cap["solves_per_s"], 3),
-            "capacity_mcell_steps_per_s": round(cap["mcell_steps_per_s"], 1),
-            "arrival_rate_per_s": round(rate, 3),
-            "batched": r(batched), "plain": r(plain),
-            "plain_capacity_solves_per_s": round(plain_cap["solves_per_s"], 3),
-            "batched_over_plain_capacity": round(cap["solves_per_s"] / plain_cap["solves_per_s"], 3)}
+            "tiles_2d": {"tuning_s": round(tune_s, 2),
+                         "band_halo": {f"{names[t['kind']]}_{t['n']}": [t["band_rows"], t["halo_rows"]]
+                                       for t in tiles}},
+            "capacity": r(cap), "arrival_rate_per_s": round(rate, 3), "batched_at_80pct": r(batched),
+            "nonphysical_rids": [f[0] for f in cap["failed"]],
+            "vs_plain": {"sample": f"every {sample_every}th request ({len(sample)})", "batched": r(cap_s),
+                         "plain": r(plain_s),
+                         "batched_over_plain_solves_per_s": round(cap_s["solves_per_s"] / plain_s["solves_per_s"], 3),
+                         "plain_at_80pct_of_batched_capacity": "overloaded: its capacity is below the arrival rate"
+                         if plain_s["solves_per_s"] < rate else "keeps up"}}
 
 
-def cpu_baseline(name):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def host_threads():
+    """Threads the oracle runs with: OMP_NUM_THREADS when set (the host's
+    share of cores), else every core the OS reports."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return int(env) if env.isdigit() and int(env) > 0 else (os.cpu_count() or 1)
+
+
+def cpu_baseline(name, steps, threads=None):
+    """The FP64 oracle, as it stands, on the first `steps` time steps of the
+    workload (threads: host_threads() unless given)."""
     from oracle import oracle as O
-    factory, _, sample_steps = WORKLOADS[name]
-    P = factory()
-    kw = dict(system=P.system, dim=P.dim, n=P.n if P.dim == 2 else (P.n[0], 1), lo=P.lo, hi=P.hi, g=P.g,
-              gamma=P.gamma, ch_factor=P.ch_factor, adv=P.adv, xi_mode=P.xi_mode, nu=P.nu, xi=P.xi,
-              omega=P.omega, c=P.c, k=P.k, bc=P.bc, T=P.T, max_steps=sample_steps)
-    cf = O.make_config(**kw)
+    from parity_util import oracle_config
+    P = WORKLOADS[name][0]()
+    threads = threads or host_threads()
+    cf = oracle_config(O, P, threads=threads, max_steps=min(P.max_steps, steps) if steps else P.max_steps)
     t0 = time.perf_counter()
     r = O.run(cf, P.U0)
     dt = time.perf_counter() - t0
+    log(f"oracle on {P.name}: {r['steps']} steps, {threads} threads, {dt:.1f} s")
     return {"value": round(P.cells * r["steps"] / dt / 1e6, 3), "unit": "Mcell-steps/s", "cores": r["threads"],
             "kind": "oracle",
             "sample": f"first {r['steps']} time steps of {P.name} (FP64 oracle, {dt:.1f} s)"}
@@ -241,18 +324,16 @@ def cpu_baseline(name):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5, help="timed full solves")
+    ap.add_argument("--steps", type=int, default=5, help="timed full solves of the headline workload")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=HEADLINE, choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-also", action="store_true", help="skip the other workloads")
-    ap.add_argument("--no-other-precision", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=200,
-                    help="requests in the serving sample (0: skip serving)")
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="requests of the serving stream (0: skip serving)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="only run three device-to-device copies of MIB MiB (a plain copy kernel of known size, "
-                         "for scaling the HBM byte counters) and exit")
+                    help="only run the library's streaming copy kernel over MIB MiB (three timed copies) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X (no multi-GPU path)",
@@ -263,20 +344,16 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     if args.calibrate_copy > 0:
-        nbytes = args.calibrate_copy << 20
-        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": 3}))
+        from paper_2608_04283_amd import vklb
+        print(json.dumps(vklb.stream_copy_bench(args.calibrate_copy << 20)))
         return
-    _, precs, _ = WORKLOADS[args.workload]
+    _, precs, _, cpu_steps, _ = WORKLOADS[args.workload]
     prec = args.precision or precs[0]
     main_res = time_workload(args.workload, prec, args.steps, args.warmup)
     out = {
-        # the headline metric; its HBM fraction is roofline.frac, FP64 is under
-        # other_precision, served solves/s and p50/p99 latency under serving
+        # the headline metric; its HBM fraction is roofline.frac, the other
+        # workloads (FP64 beside FP32) under also, served solves/s with p50/p99
+        # latency under serving
         "metric": "Mcell-steps/s & % HBM roofline, FP32 vs FP64; served solves/s, p50/p99 latency",
         "value": round(main_res["value"], 2),
         "unit": "Mcell-steps/s",
@@ -289,31 +366,39 @@ def main():
         "vs_baseline": None,
         "dtype": main_res["dtype"],
         "data": "synthetic",
-        "config": {"workload": main_res["workload"], "cells": main_res["cells"],
-                   "time_steps_per_solve": main_res["steps_per_solve"], "t_end": main_res["t_end"],
-                   "lattice": "D1Q3" if "1d" in args.workload else "D2Q5", "omega": 1.0, "c": 0.05, "k": 2.0},
+        "config": dict({"workload": main_res["workload"], "cells": main_res["cells"],
+                        "time_steps_per_solve": main_res["steps_per_solve"], "t_end": main_res["t_end"]},
+                       **main_res["params"]),
         "roofline": main_res["roofline"],
         "error_vs_oracle": main_res["error"],
     }
+    if main_res.get("exact"):
+        out["error_vs_exact"] = main_res["exact"]
+    if "max_div_b" in main_res:
+        out["max_div_b"] = main_res["max_div_b"]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.workload)
-    extra = {}
-    for p2 in precs:
-        if p2 != prec and not args.no_other_precision:
-            r = time_workload(args.workload, p2, max(1, args.steps // 2), 1)
-            extra[p2] = {"value": round(r["value"], 2), "ms_per_solve": round(r["ms_per_solve"], 4),
-                         "roofline": r["roofline"], "error_vs_oracle": r["error"]}
-    if extra:
-        out["other_precision"] = extra
+        cb = cpu_baseline(args.workload, cpu_steps)
+        cb["cpu_model"] = cpu_model()
+        one = cpu_baseline(args.workload, max(1, (cpu_steps or 20) // 10), threads=1)
+        cb["single_thread"] = {"value": one["value"], "sample": one["sample"]}
+        out["cpu_baseline"] = cb
     if not args.no_also:
         also = {}
-        for name, (_, wprecs, _) in WORKLOADS.items():
-            if name == args.workload:
-                continue
-            r = time_workload(name, wprecs[0], 2, 1)
-            also[name] = {"value": round(r["value"], 2), "dtype": r["dtype"], "ms_per_solve": round(r["ms_per_solve"], 3),
-                          "steps_per_solve": r["steps_per_solve"], "roofline": r["roofline"],
-                          "error_vs_oracle": r["error"]}
+        for name, (_, wprecs, (w, k), csteps, _) in WORKLOADS.items():
+            for p2 in wprecs:
+                if name == args.workload and p2 == prec:
+                    continue
+                r = time_workload(name, p2, k, w)
+                entry = {"workload": r["workload"], "value": round(r["value"], 2), "dtype": r["dtype"],
+                         "ms_per_solve": round(r["ms_per_solve"], 3), "steps_per_solve": r["steps_per_solve"],
+                         "params": r["params"], "roofline": r["roofline"], "error_vs_oracle": r["error"]}
+                if r.get("exact"):
+                    entry["error_vs_exact"] = r["exact"]
+                if "max_div_b" in r:
+                    entry["max_div_b"] = r["max_div_b"]
+                if p2 == wprecs[0] and not args.no_cpu_baseline and name != args.workload:
+                    entry["cpu_baseline"] = cpu_baseline(name, csteps)
+                also[f"{name}_{p2}"] = entry
         out["also"] = also
     if args.serving_requests > 0:
         out["serving"] = serving_bench(args.serving_requests)
