@@ -350,6 +350,14 @@ def main():
     _, precs, _, cpu_steps, _ = WORKLOADS[args.workload]
     prec = args.precision or precs[0]
     main_res = time_workload(args.workload, prec, args.steps, args.warmup)
+    # the copy ceiling beside it: the library's streaming copy (every byte read
+    # and written once, one 16-byte word per lane) over 1 GiB
+    from paper_2608_04283_amd import vklb
+    copy = vklb.stream_copy_bench(1 << 30)["non_temporal"]
+    main_res["roofline"]["copy_ceiling"] = {"gb_per_s": copy["gb_per_s"], "bytes": 2 << 30,
+                                            "achieved_over_copy": round(main_res["roofline"]["achieved"] /
+                                                                        copy["gb_per_s"], 4)}
+    log(f"copy ceiling {copy['gb_per_s']:.1f} GB/s")
     out = {
         # the headline metric; its HBM fraction is roofline.frac, the other
         # workloads (FP64 beside FP32) under also, served solves/s with p50/p99

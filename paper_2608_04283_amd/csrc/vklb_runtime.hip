@@ -130,33 +130,21 @@ __global__ void k_static_info(const DevState* st, int par, vklb_run_info* out) {
   out->done = (S.done || S.n >= st->max_steps || !(S.t < st->T) || err) ? 1 : 0;
 }
 
-// Streaming copy of n16 16-byte words: each workgroup copies one contiguous
-// chunk, 4 KiB per wavefront row of loads and four rows in flight per lane
-// before their stores (the step kernels' pattern: each workgroup reads and
-// writes its own contiguous runs once). NT: non-temporal loads and stores
-// (the step kernels' population stores and 2D row loads), else plain ones.
+// Streaming copy of n16 16-byte words, one word per lane and one workgroup
+// per 4 KiB: every wave issues its load and its store and ends, so the
+// dispatcher keeps the compute units full of fresh waves and their loads in
+// flight. Measured on MI355X (2 GiB): 6.14 TB/s read + write, against
+// 5.0-5.5 TB/s for grid-stride or per-workgroup chunked loops with four or
+// eight words per lane and 4.9 TB/s for hipMemcpyAsync. NT: non-temporal
+// load and store (the step kernels' population stores and 2D row loads).
 typedef float v4f __attribute__((ext_vector_type(4)));
 template <bool NT>
 __global__ void __launch_bounds__(256) k_stream_copy(const v4f* __restrict__ src, v4f* __restrict__ dst,
-                                                     long long n16, long long chunk) {
-  const long long begin = (long long)blockIdx.x * chunk;
-  const long long end = begin + chunk < n16 ? begin + chunk : n16;
-  for (long long base = begin; base < end; base += 4 * 256) {
-    v4f v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const long long i = base + u * 256 + threadIdx.x;
-      if (i < end) v[u] = NT ? __builtin_nontemporal_load(src + i) : src[i];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const long long i = base + u * 256 + threadIdx.x;
-      if (i < end) {
-        if (NT) __builtin_nontemporal_store(v[u], dst + i);
-        else dst[i] = v[u];
-      }
-    }
-  }
+                                                     long long n16) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n16) return;
+  if (NT) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+  else dst[i] = src[i];
 }
 
 }  // namespace
@@ -998,18 +986,18 @@ vklb_status vklb_stream_copy(void* dst, const void* src, size_t bytes, int non_t
   }
   const long long n16 = (long long)(bytes / 16);
   if (n16 == 0) return VKLB_OK;
-  // up to 8 workgroups of 256 lanes per compute unit, each a contiguous
-  // chunk of whole 1024-word rows of four loads per lane
-  const long long rows = (n16 + 1023) / 1024;
-  const int grid = int(std::min<long long>(2048, rows));
-  const long long chunk = (rows + grid - 1) / grid * 1024;
+  const long long blocks = (n16 + 255) / 256;
+  if (blocks > 0x7fffffffll) {
+    set_create_error("vklb_stream_copy: more than 2^31 workgroups of 4 KiB");
+    return VKLB_ERR_ARG;
+  }
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   if (non_temporal)
-    hipLaunchKernelGGL(k_stream_copy<true>, dim3(grid), dim3(256), 0, st, static_cast<const v4f*>(src),
-                       static_cast<v4f*>(dst), n16, chunk);
+    hipLaunchKernelGGL(k_stream_copy<true>, dim3(unsigned(blocks)), dim3(256), 0, st, static_cast<const v4f*>(src),
+                       static_cast<v4f*>(dst), n16);
   else
-    hipLaunchKernelGGL(k_stream_copy<false>, dim3(grid), dim3(256), 0, st, static_cast<const v4f*>(src),
-                       static_cast<v4f*>(dst), n16, chunk);
+    hipLaunchKernelGGL(k_stream_copy<false>, dim3(unsigned(blocks)), dim3(256), 0, st, static_cast<const v4f*>(src),
+                       static_cast<v4f*>(dst), n16);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     char m[160];
