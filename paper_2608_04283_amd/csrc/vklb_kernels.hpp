@@ -838,6 +838,9 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
   // row is collided, so a row's memory latency overlaps the previous row's
   // work; MHD has no registers to spare for it.
   constexpr bool PREFETCH = Q * P <= 20;
+  // Rows whose loads are in flight ahead of the one being collided (SW and
+  // Euler): each lane keeps this many rows of stored values in registers.
+  constexpr int AHEAD = PREFETCH ? 2 : 0;
   // In the delta bases the rows next to the band and the halo columns use one
   // population each: they load only U and that population and collide it with
   // the split of its axis alone.
@@ -853,11 +856,20 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
   constexpr int PS = ALTERNATE ? 3 : 4;
   // Stored values of the row before the band (its population in slot 3 of
   // the array whichever it is) and of the first row.
-  T fpre[Q][P], fraw[Q][P], lo[P], fnext[Q][P], lonext[P];
+  T fpre[Q][P], fraw[Q][P], lo[P], fnext[Q][P], lonext[P], fnext2[Q][P], lonext2[P];
   auto load_first = [&]() {
     if (PARTIAL) K::load_one(src, pre, qpre, fpre[REST], fpre[3]);
     else K::load(src, pre, fpre);
     K::load_stream(src, row_of(0) * nx + xl, fraw, lo);
+    if (AHEAD == 2) {
+      // the second row (or, in a one-row band, the row after the band)
+      if (nr > 1) {
+        K::load_stream(src, row_of(1) * nx + xl, fnext, lonext);
+      } else {
+        if (PARTIAL) K::load_one(src, post, qpost, fnext[REST], fnext[PS]);
+        else K::load(src, post, fnext);
+      }
+    }
   };
   load_first();
   double pa, pb;
@@ -959,12 +971,16 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
     }
     // collide row r; the first row was loaded before the partials reduction
     if (PREFETCH) {
-      if (i + 1 < nr) {
-        K::load_stream(src, row_of(i + 1) * nx + xl, fnext, lonext);
-      } else if (PARTIAL) {
-        K::load_one(src, post, qpost, fnext[REST], fnext[PS]);
-      } else {
-        K::load(src, post, fnext);
+      // the row AHEAD rows on (row i + 1 came with the previous iteration
+      // when AHEAD is 2), or the row after the band
+      const int k = i + AHEAD;
+      T(&dstf)[Q][P] = AHEAD == 2 ? fnext2 : fnext;
+      T(&dstl)[P] = AHEAD == 2 ? lonext2 : lonext;
+      if (k < nr) {
+        K::load_stream(src, row_of(k) * nx + xl, dstf, dstl);
+      } else if (k == nr) {
+        if (PARTIAL) K::load_one(src, post, qpost, dstf[REST], dstf[PS]);
+        else K::load(src, post, dstf);
       }
     } else if (i > 0) {
       K::load_stream(src, r * nx + xl, fraw, lo);
@@ -990,10 +1006,16 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
 #pragma unroll
       for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int v = 0; v < P; ++v) fraw[q][v] = fnext[q][v];
+        for (int v = 0; v < P; ++v) {
+          fraw[q][v] = fnext[q][v];
+          if (AHEAD == 2) fnext[q][v] = fnext2[q][v];
+        }
       if (K::COMP) {
 #pragma unroll
-        for (int v = 0; v < P; ++v) lo[v] = lonext[v];
+        for (int v = 0; v < P; ++v) {
+          lo[v] = lonext[v];
+          if (AHEAD == 2) lonext[v] = lonext2[v];
+        }
       }
     }
   };
