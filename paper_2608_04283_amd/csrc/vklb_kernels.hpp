@@ -76,6 +76,39 @@ struct SolveDesc {
                          // each launch's partials are folded into entry 0 after it
 };
 
+// Global-memory views of a solve's device pointers. The single-solve kernels
+// take the descriptor as a kernel argument, whose pointers the compiler
+// already treats as global memory; the batched kernel reads descriptors from
+// a table in memory, and through plain pointers its loads and stores would be
+// flat instructions, which also count against the LDS wait counter, so every
+// LDS read of the row march would wait for the row loads in flight. All
+// accesses of the per-step path go through these views.
+template <class T>
+using gmem = __attribute__((address_space(1))) T;
+template <class T>
+__device__ inline gmem<T>* gl(T* p) {
+  return (gmem<T>*)p;
+}
+// Scalars of parity p: load and store field by field (address-space-qualified
+// structs have no implicit copy).
+__device__ inline Scal load_scal(const gmem<DevState>* st, int p) {
+  Scal r;
+  r.t = st->S[p].t;
+  r.n = st->S[p].n;
+  r.done = st->S[p].done;
+  r.pad = 0;
+  return r;
+}
+__device__ inline void store_scal(gmem<DevState>* st, int p, const Scal& v) {
+  st->S[p].t = v.t;
+  st->S[p].n = v.n;
+  st->S[p].done = v.done;
+  st->S[p].pad = v.pad;
+}
+__device__ inline void report_cell(const SolveDesc& sd, unsigned long long word) {
+  __hip_atomic_fetch_min(&gl(sd.st)->err_word, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Values every workgroup derives at the start of a step.
 struct Step {
   double t, xi, lam, ch, T;
@@ -206,9 +239,9 @@ struct StateIn {
 };
 
 __device__ inline StateIn read_state(const SolveDesc& sd) {
-  const DevState* st = sd.st;
+  const gmem<DevState>* st = gl(sd.st);
   StateIn r;
-  r.S = st->S[sd.par];
+  r.S = load_scal(st, sd.par);
   r.T = st->T;
   r.max_steps = st->max_steps;
   r.err = st->err_word != ~0ull;
@@ -221,7 +254,7 @@ __device__ inline StateIn read_state(const SolveDesc& sd) {
 // leaves the max unchanged.
 template <bool TWO = true>
 __device__ inline void load_partials(const SolveDesc& sd, int lanes, double& a, double& b) {
-  const double* pl = sd.part + (long long)sd.par * 2 * sd.nblocks;
+  const gmem<double>* pl = gl(sd.part) + (long long)sd.par * 2 * sd.nblocks;
   const int last = sd.nred - 1;
   const int i0 = min((int)threadIdx.x, last), i1 = min((int)threadIdx.x + lanes, last);
   a = fmax(pl[i0], pl[i1]);
@@ -235,8 +268,8 @@ __device__ inline void load_partials(const SolveDesc& sd, int lanes, double& a, 
 template <bool TWO = true>
 __device__ inline Step begin_step(const SolveDesc& sd, double* red, int lanes, const StateIn& in, double a,
                                   double b) {
-  const double* pl = sd.part + (long long)sd.par * 2 * sd.nblocks;
-  const double* pc = pl + sd.nblocks;
+  const gmem<double>* pl = gl(sd.part) + (long long)sd.par * 2 * sd.nblocks;
+  const gmem<double>* pc = pl + sd.nblocks;
   for (int i = threadIdx.x + 2 * lanes; i < sd.nred; i += lanes) {
     a = fmax(a, pl[i]);
     if (TWO) b = fmax(b, pc[i]);
@@ -265,7 +298,7 @@ __device__ inline int predicted_parity(const SolveDesc& sd) { return (sd.par ^ s
 // advances (t, n) for it, or carries a finished state over unchanged.
 __device__ inline void end_step(const SolveDesc& sd, const Step& S, int tile, double lam, double cfm) {
   const int np = sd.par ^ 1;
-  double* pl = sd.part + (long long)np * 2 * sd.nblocks;
+  gmem<double>* pl = gl(sd.part) + (long long)np * 2 * sd.nblocks;
   if (threadIdx.x == 0) {
     pl[tile] = lam;
     pl[sd.nblocks + tile] = cfm;
@@ -275,7 +308,7 @@ __device__ inline void end_step(const SolveDesc& sd, const Step& S, int tile, do
       nx.n = S.n + 1;
       nx.done = 0;
       nx.pad = 0;
-      sd.st->S[np] = nx;
+      store_scal(gl(sd.st), np, nx);
     }
   }
 }
@@ -284,8 +317,8 @@ __device__ inline void end_step(const SolveDesc& sd, const Step& S, int tile, do
 // maxima of the final state) over to the other parity unchanged.
 __device__ inline void carry_done(const SolveDesc& sd, const Step& S, int tile) {
   if (tile != 0) return;
-  const double* src = sd.part + (long long)sd.par * 2 * sd.nblocks;
-  double* dst = sd.part + (long long)(sd.par ^ 1) * 2 * sd.nblocks;
+  const gmem<double>* src = gl(sd.part) + (long long)sd.par * 2 * sd.nblocks;
+  gmem<double>* dst = gl(sd.part) + (long long)(sd.par ^ 1) * 2 * sd.nblocks;
   for (int i = threadIdx.x; i < 2 * sd.nblocks; i += blockDim.x) dst[i] = src[i];
   if (threadIdx.x == 0) {
     Scal nx;
@@ -293,7 +326,7 @@ __device__ inline void carry_done(const SolveDesc& sd, const Step& S, int tile) 
     nx.n = S.n;
     nx.done = 1;
     nx.pad = 0;
-    sd.st->S[sd.par ^ 1] = nx;
+    store_scal(gl(sd.st), sd.par ^ 1, nx);
   }
 }
 
@@ -325,7 +358,9 @@ struct Kern {
     return ((cell >> kBlockLog2) * PLANES + plane) * kBlock + (cell & (kBlock - 1));
   }
 
-  __device__ static inline void load(const T* __restrict__ src, long long cell, T (&f)[Q][P]) {
+  // (SP: a pointer to const T, plain or global; see gmem)
+  template <class SP>
+  __device__ static inline void load(SP __restrict__ src, long long cell, T (&f)[Q][P]) {
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -336,7 +371,8 @@ struct Kern {
   // reads: non-temporal loads, so those lines leave L2 before the halo-column
   // and edge-row lines that neighbouring workgroups read again. (1D steps keep
   // plain loads: their cells stay cache-resident from one launch to the next.)
-  __device__ static inline void load_stream(const T* __restrict__ src, long long cell, T (&f)[Q][P], T (&lo)[P]) {
+  template <class SP>
+  __device__ static inline void load_stream(SP __restrict__ src, long long cell, T (&f)[Q][P], T (&lo)[P]) {
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -346,7 +382,8 @@ struct Kern {
   }
 
   // Low part of U (compensated basis only).
-  __device__ static inline void load_lo(const T* __restrict__ src, long long cell, T (&lo)[P]) {
+  template <class SP>
+  __device__ static inline void load_lo(SP __restrict__ src, long long cell, T (&lo)[P]) {
 #pragma unroll
     for (int v = 0; v < P; ++v) lo[v] = COMP ? src[pidx(Q * P + v, cell)] : T(0);
   }
@@ -397,8 +434,8 @@ struct Kern {
   }
 
   // Delta bases, 2D: load only U (rest slot) and population q of a cell.
-  __device__ static inline void load_one(const T* __restrict__ src, long long cell, int q, T (&Ur)[P],
-                                         T (&fq)[P]) {
+  template <class SP>
+  __device__ static inline void load_one(SP __restrict__ src, long long cell, int q, T (&Ur)[P], T (&fq)[P]) {
 #pragma unroll
     for (int v = 0; v < P; ++v) {
       Ur[v] = src[pidx(REST * P + v, cell)];
@@ -422,7 +459,8 @@ struct Kern {
   }
 
   // One stored slot (p values) of a strip row, non-temporal (see load_stream).
-  __device__ static inline void load_slot_stream(const T* __restrict__ src, long long cell, int slot, T (&f)[P]) {
+  template <class SP>
+  __device__ static inline void load_slot_stream(SP __restrict__ src, long long cell, int slot, T (&f)[P]) {
 #pragma unroll
     for (int v = 0; v < P; ++v) f[v] = __builtin_nontemporal_load(&src[pidx(slot * P + v, cell)]);
   }
@@ -448,7 +486,8 @@ struct Kern {
 
   // U of a stored cell: the rest slot in the delta bases, else the sum of
   // the populations (in the order relax takes them).
-  __device__ static inline void moments_of(const T* __restrict__ src, long long cell, T (&U)[P]) {
+  template <class SP>
+  __device__ static inline void moments_of(SP __restrict__ src, long long cell, T (&U)[P]) {
 #pragma unroll
     for (int v = 0; v < P; ++v) {
       if (DELTA) {
@@ -462,8 +501,9 @@ struct Kern {
     }
   }
 
-  __device__ static inline void collide(const T* __restrict__ src, long long cell, const Phys& ph,
-                                        double ixi, double Lam, double ch, T (&fs)[Q][P], T (&U)[P]) {
+  template <class SP>
+  __device__ static inline void collide(SP __restrict__ src, long long cell, const Phys& ph, double ixi,
+                                        double Lam, double ch, T (&fs)[Q][P], T (&U)[P]) {
     T f[Q][P];
     load(src, cell, f);
     relax(f, ph, ixi, Lam, ch, fs, U);
@@ -480,7 +520,7 @@ struct Kern {
     Cell<KIND, DIM, ST>::speeds(Us, sd.ph, &l, &c);
     const bool bad = !Cell<KIND, DIM, ST>::admissible(Us, sd.ph);
     if (bad) {
-      atomicMin(&sd.st->err_word, ((unsigned long long)step << 32) | (unsigned long long)cell);
+      report_cell(sd, ((unsigned long long)step << 32) | (unsigned long long)cell);
       l = ST(0);
       c = ST(0);
     }
@@ -511,8 +551,8 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
   const StateIn in = read_state(sd);
   const int bp = predicted_parity(sd);
   T f[Q][P], lo[P];
-  K::load((const T*)(bp ? sd.fb : sd.fa), xl, f);
-  K::load_lo((const T*)(bp ? sd.fb : sd.fa), xl, lo);
+  K::load(gl((const T*)(bp ? sd.fb : sd.fa)), xl, f);
+  K::load_lo(gl((const T*)(bp ? sd.fb : sd.fa)), xl, lo);
   double pa, pb;
   load_partials<KIND == K_MHD>(sd, B, pa, pb);
   const Step S = begin_step<KIND == K_MHD>(sd, red, B, in, pa, pb);
@@ -522,10 +562,10 @@ __device__ inline void step1d_tile(const SolveDesc& sd, int tile) {
   }
   const long long n = S.n;
   if (int(n & 1) != bp) {
-    K::load((const T*)((n & 1) ? sd.fb : sd.fa), xl, f);
-    K::load_lo((const T*)((n & 1) ? sd.fb : sd.fa), xl, lo);
+    K::load(gl((const T*)((n & 1) ? sd.fb : sd.fa)), xl, f);
+    K::load_lo(gl((const T*)((n & 1) ? sd.fb : sd.fa)), xl, lo);
   }
-  T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
+  gmem<T>* __restrict__ dst = gl((T*)((n & 1) ? sd.fa : sd.fb));
   const double ixi = 1.0 / S.xi, Lam = S.lam, ch = S.ch;
 
   __shared__ T s_plus[P][B], s_minus[P][B];
@@ -833,7 +873,7 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
   auto row_of = [&](int i) { return down ? y1 - 1 - i : y0 + i; };
   const StateIn in = read_state(sd);
   const int bp = predicted_parity(sd);
-  const T* __restrict__ src = (const T*)(bp ? sd.fb : sd.fa);
+  const gmem<T>* __restrict__ src = gl((const T*)(bp ? sd.fb : sd.fa));
   // Systems with few values per cell (SW, Euler) load the next row while a
   // row is collided, so a row's memory latency overlaps the previous row's
   // work; MHD has no registers to spare for it.
@@ -881,10 +921,10 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
   }
   const long long n = S.n;
   if (int(n & 1) != bp) {
-    src = (const T*)((n & 1) ? sd.fb : sd.fa);
+    src = gl((const T*)((n & 1) ? sd.fb : sd.fa));
     load_first();
   }
-  T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
+  gmem<T>* __restrict__ dst = gl((T*)((n & 1) ? sd.fa : sd.fb));
   const double ixi = 1.0 / S.xi, Lam = S.lam, ch = S.ch;
 
   __shared__ T s_ex[3][2][P][W];      // march slot, (+x, -x), var, lane
@@ -1082,7 +1122,7 @@ __device__ inline void step2d_tile_axes(const SolveDesc& sd, int tile) {
   auto row_of = [&](int i) { return down ? y1 - 1 - i : y0 + i; };
   const StateIn in = read_state(sd);
   const int bp = predicted_parity(sd);
-  const T* __restrict__ src = (const T*)(bp ? sd.fb : sd.fa);
+  const gmem<T>* __restrict__ src = gl((const T*)(bp ? sd.fb : sd.fa));
   const long long below = (long long)map_index(y0 - 1, ny, sd.bcy) * nx + xl;
   const long long above = (long long)map_index(y1, ny, sd.bcy) * nx + xl;
   const long long pre = down ? above : below, post = down ? below : above;
@@ -1127,10 +1167,10 @@ __device__ inline void step2d_tile_axes(const SolveDesc& sd, int tile) {
   }
   const long long n = S.n;
   if (int(n & 1) != bp) {
-    src = (const T*)((n & 1) ? sd.fb : sd.fa);
+    src = gl((const T*)((n & 1) ? sd.fb : sd.fa));
     load_first();
   }
-  T* __restrict__ dst = (T*)((n & 1) ? sd.fa : sd.fb);
+  gmem<T>* __restrict__ dst = gl((T*)((n & 1) ? sd.fa : sd.fb));
   const double ixi = 1.0 / S.xi, Lam = S.lam, ch = S.ch;
 
   constexpr int HMAX = 64;            // band rows (vklb_options.band_rows <= 64 here)
