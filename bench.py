@@ -54,7 +54,7 @@ WORKLOADS = {
     "sw1d_dambreak": (lambda: I.dam_break(1000), ("fp64",), (1, 3), None, "D1Q3"),
     "sw1d_dambreak_d1q2": (lambda: I.dam_break(1000, c=0.5, k=0.0), ("fp64",), (1, 3), None, "D1Q2"),
     "mhd1d_briowu": (lambda: I.brio_wu(16384), ("fp32",), (1, 2), 400, "D1Q3"),
-    "mhd2d_orszag_tang": (lambda: I.orszag_tang(1024, steps=1000), ("fp32",), (1, 3), 2, "D2Q5"),
+    "mhd2d_orszag_tang": (lambda: I.orszag_tang(1024, steps=1000), ("fp32",), (1, 3), 10, "D2Q5"),
 }
 HEADLINE = "euler2d_quadrants"
 
@@ -261,8 +261,13 @@ def serving_bench(count, seed=1, budget=None, sample_every=5):
     reqs = I.serving_requests(count, seed=seed)
     cell_steps = sum(r.problem.cells * r.steps for r in reqs)
     keep = ("solves", "ok", "nonphysical", "makespan_s", "solves_per_s", "completed_per_s", "p50_s", "p99_s",
-            "mcell_steps_per_s", "graph_launches", "graph_captures")
-    r = lambda d: {k: (round(d[k], 4) if isinstance(d[k], float) else d[k]) for k in keep if k in d}
+            "mcell_steps_per_s", "alg_gb_per_s", "hbm_frac", "graph_launches", "graph_captures")
+
+    def r(d):
+        # the stream's aggregate algorithmic bytes (2 Q p s per cell-step of
+        # every completed solve) over the makespan, as a fraction of 8 TB/s
+        d = dict(d, hbm_frac=d["alg_gb_per_s"] / 8000.0)
+        return {k: (round(d[k], 4) if isinstance(d[k], float) else d[k]) for k in keep if k in d}
     log(f"serving: 2D tile shapes tuned in {tune_s:.1f} s")
     prog = lambda what: (lambda k, n: log(f"serving {what}: {k} of {n} solves done"))
     cap = serving.run_batched(reqs, budget, "fp32", realtime=False, progress=prog("capacity"))

@@ -75,6 +75,12 @@ def tune_shapes(precision="fp32", steps=20, seed=11, sizes=TUNE_SIZES):
         pool.close()
 
 
+def _alg_bytes(prob, precision):
+    """Algorithmic bytes of one cell-step: every population read once and
+    written once, 2 Q p s."""
+    return 2 * prob.Q * prob.p * (4 if precision == "fp32" else 8)
+
+
 def run_batched(requests, budget_bytes, precision="fp32", chunk_rounds=32, realtime=True, keep_results=False,
                 progress=None):
     """Serve `requests` (inputs.Request, sorted by arrival) through a pool;
@@ -87,6 +93,7 @@ def run_batched(requests, budget_bytes, precision="fp32", chunk_rounds=32, realt
     latencies = []
     results = {}
     cell_steps = 0
+    alg_bytes = 0
     n_done = 0
     failed = []
     t0 = time.perf_counter()
@@ -108,6 +115,7 @@ def run_batched(requests, budget_bytes, precision="fp32", chunk_rounds=32, realt
                 t_done = time.perf_counter() - t0
                 latencies.append(t_done - arrival[c["tag"]])
                 cell_steps += c["problem"].cells * c["steps"]
+                alg_bytes += c["problem"].cells * c["steps"] * _alg_bytes(c["problem"], precision)
                 n_done += 1
                 if progress and n_done % 200 == 0:
                     progress(n_done, len(reqs))
@@ -125,6 +133,7 @@ def run_batched(requests, budget_bytes, precision="fp32", chunk_rounds=32, realt
     return {"mode": "batched", "solves": n_done, "ok": ok, "makespan_s": makespan, "solves_per_s": ok / makespan,
             "completed_per_s": n_done / makespan,
             "p50_s": p50, "p99_s": p99, "cell_steps": cell_steps, "mcell_steps_per_s": cell_steps / makespan / 1e6,
+            "alg_gb_per_s": alg_bytes / makespan / 1e9,
             "nonphysical": len(failed), "failed": failed, "arena_peak_bytes": stats["arena_peak"],
             "rounds": stats["rounds"], "graph_launches": stats["graph_launches"],
             "graph_captures": stats["graph_captures"],
@@ -140,6 +149,7 @@ def run_plain(requests, precision="fp32", realtime=True, keep_results=False, gra
     latencies = []
     results = {}
     cell_steps = 0
+    alg_bytes = 0
     failed = []
     t0 = time.perf_counter()
     try:
@@ -164,6 +174,7 @@ def run_plain(requests, precision="fp32", realtime=True, keep_results=False, gra
             t_done = time.perf_counter() - t0
             latencies.append(t_done - (rq.arrival if realtime else 0.0))
             cell_steps += prob.cells * n
+            alg_bytes += prob.cells * n * _alg_bytes(prob, precision)
             if progress and len(latencies) % 100 == 0:
                 progress(len(latencies), len(reqs))
             if keep_results:
@@ -176,6 +187,7 @@ def run_plain(requests, precision="fp32", realtime=True, keep_results=False, gra
     return {"mode": "plain", "solves": len(reqs), "ok": ok, "makespan_s": makespan, "solves_per_s": ok / makespan,
             "completed_per_s": len(reqs) / makespan,
             "p50_s": p50, "p99_s": p99, "cell_steps": cell_steps, "mcell_steps_per_s": cell_steps / makespan / 1e6,
+            "alg_gb_per_s": alg_bytes / makespan / 1e9,
             "nonphysical": len(failed), "failed": failed, "results": results if keep_results else None}
 
 
