@@ -59,6 +59,15 @@ inline long long max_step_blocks(const vklb_grid* g) {
   return ((g->n[0] + 63) / 64) * g->n[1];
 }
 
+// Cells from one row to the next in the population buffers: nx in 1D; in 2D
+// nx rounded up to a multiple of 64, so that the 64 cells of a row a
+// wavefront loads or stores start at a multiple of 64 whatever nx is, and
+// each of its plane accesses is one aligned run of the blocked layout. The
+// padding cells are never read or written by a step.
+inline long long row_stride(const vklb_grid* g) {
+  return g->dim == 2 ? (g->n[0] + 63) / 64 * 64 : g->n[0];
+}
+
 // basis: as resolve_basis returns it (sizes the population buffers).
 inline bool layout_of(const vklb_system* sys, vklb_lattice lat, const vklb_grid* g, vklb_precision prec, int basis,
                       Layout* L) {
@@ -71,11 +80,14 @@ inline bool layout_of(const vklb_system* sys, vklb_lattice lat, const vklb_grid*
   if (nx < 1 || ny < 1 || nx > (1ll << 30) || ny > (1ll << 30)) return false;
   const long long cells = nx * ny;
   if (cells > (1ll << 31) - 1) return false;
+  // population buffers: padded rows in 2D (64-bit indices on the device; the
+  // 2^31 limit is on natural cell indices, which non-physical reports carry)
+  const long long pcells = row_stride(g) * ny;
   L->p = p;
   L->Q = g->dim == 1 ? 3 : 5;
   L->slots = L->Q + (basis == 2 ? 1 : 0);
   L->elem = prec == VKLB_FP32 ? 4 : 8;
-  L->stride = (cells + kBlock - 1) / kBlock * kBlock;  // whole storage blocks
+  L->stride = (pcells + kBlock - 1) / kBlock * kBlock;  // whole storage blocks
   const size_t plane = size_t(L->stride) * L->elem;
   L->state_off = 0;
   L->stage_off = align_up(sizeof(DevState));
@@ -203,6 +215,7 @@ inline SolveDesc make_desc(char* base, const Layout& L, const vklb_system* sys, 
   d.xi_mode = lambda->mode == VKLB_XI_CFL ? 0 : 1;
   d.nx = int(grid->n[0]);
   d.ny = grid->dim == 2 ? int(grid->n[1]) : 1;
+  d.sx = int(row_stride(grid));
   d.stride = L.stride;
   d.bcx = bc[0] == VKLB_BC_PERIODIC ? 0 : (bc[0] == VKLB_BC_CHARACTERISTIC ? 2 : 1);
   d.bcy = (grid->dim == 2 ? bc[1] : bc[0]) == VKLB_BC_PERIODIC ? 0 : 1;

@@ -1,7 +1,10 @@
 // Device kernels of the WU-VKLB step for gfx950 (one fused kernel per step).
 //
-// Data layout in HBM: cell = j * nx + i; cells are grouped in blocks of 256
-// consecutive cells and each block stores its stored values plane after plane
+// Data layout in HBM: cell = j * sx + i, with the row stride sx = nx in 1D and
+// nx rounded up to a multiple of 64 in 2D (the padding cells are never read),
+// so that every wavefront's 64 cells of a row start at a multiple of 64 and
+// each of its plane loads is one aligned run; cells are grouped in blocks of
+// 256 consecutive cells and each block stores its stored values plane after plane
 // (plane = slot * P + var, 256 values each): structure of arrays inside a
 // block, so every load and store of a wavefront is one contiguous 256-byte
 // (FP32) run and a workgroup row touches one region, not Q * P far-apart
@@ -65,7 +68,8 @@ struct SolveDesc {
   double xi_fixed;
   int xi_mode;           // 0 CFL, 1 fixed
   int nx, ny;            // ny = 1 in 1D
-  long long stride;      // cells rounded up to whole 256-cell blocks
+  int sx;                // population buffers: cells from one row to the next (row_stride)
+  long long stride;      // population buffers: cells (sx * ny) rounded up to whole 256-cell blocks
   int bcx, bcy;          // 0 periodic, 1 zero gradient
   int nblocks;           // workgroups per step launch (= number of partials)
   int band;              // 2D rows per band
@@ -855,6 +859,7 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
   constexpr int P = K::P, Q = 5, REST = 2;
   __shared__ double red[2 * (W / 64) + 2], red_end[2 * (W / 64) + 2];
   const int nx = sd.nx, ny = sd.ny, H = sd.band;
+  const long long rs = sd.sx;  // row stride of the population buffers
   const int nsx = (nx + W - 1) / W;
   const int sx = tile % nsx, sy = tile / nsx;
   const int x0 = sx * W, y0 = sy * H, y1 = min(y0 + H, ny), nr = y1 - y0;
@@ -887,8 +892,8 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
   constexpr bool PARTIAL = DELTA;
   // The row before the band in march order streams one population into its
   // first row (y0 - 1: +y up; y1: -y down); the row after it, into its last.
-  const long long below = (long long)map_index(y0 - 1, ny, sd.bcy) * nx + xl;
-  const long long above = (long long)map_index(y1, ny, sd.bcy) * nx + xl;
+  const long long below = (long long)map_index(y0 - 1, ny, sd.bcy) * rs + xl;
+  const long long above = (long long)map_index(y1, ny, sd.bcy) * rs + xl;
   const long long pre = down ? above : below, post = down ? below : above;
   const int qpre = down ? 4 : 3, qpost = down ? 3 : 4;
   // Array slot that receives the row after the band's population (fixed, so
@@ -900,11 +905,11 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
   auto load_first = [&]() {
     if (PARTIAL) K::load_one(src, pre, qpre, fpre[REST], fpre[3]);
     else K::load(src, pre, fpre);
-    K::load_stream(src, row_of(0) * nx + xl, fraw, lo);
+    K::load_stream(src, row_of(0) * rs + xl, fraw, lo);
     if (AHEAD == 2) {
       // the second row (or, in a one-row band, the row after the band)
       if (nr > 1) {
-        K::load_stream(src, row_of(1) * nx + xl, fnext, lonext);
+        K::load_stream(src, row_of(1) * rs + xl, fnext, lonext);
       } else {
         if (PARTIAL) K::load_one(src, post, qpost, fnext[REST], fnext[PS]);
         else K::load(src, post, fnext);
@@ -960,7 +965,8 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
     const int ps = (ALTERNATE ? j : rr) % 3;
     const int rb = j / hb;
     const int hbuf = rb % 3, hr = j - rb * hb;
-    const long long cell = (long long)rr * nx + x;
+    const long long cell = (long long)rr * nx + x;  // reported for a non-physical state
+    const long long pc = (long long)rr * rs + x;    // in the population buffers
     T Un[P];
 #pragma unroll
     for (int v = 0; v < P; ++v) {
@@ -968,19 +974,19 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
       const T a2 = tid < W - 1 ? s_ex[ps][1][v][tid + 1] : s_halo[hbuf][1][hr][v];
       const T a4 = down ? fs[3][v] : prevm[v];
       const T a5 = down ? prevm[v] : fs[4][v];
-      __builtin_nontemporal_store(a1, &dst[K::pidx(0 * P + v, cell)]);
-      __builtin_nontemporal_store(a2, &dst[K::pidx(1 * P + v, cell)]);
-      __builtin_nontemporal_store(a4, &dst[K::pidx(3 * P + v, cell)]);
-      __builtin_nontemporal_store(a5, &dst[K::pidx(4 * P + v, cell)]);
+      __builtin_nontemporal_store(a1, &dst[K::pidx(0 * P + v, pc)]);
+      __builtin_nontemporal_store(a2, &dst[K::pidx(1 * P + v, pc)]);
+      __builtin_nontemporal_store(a4, &dst[K::pidx(3 * P + v, pc)]);
+      __builtin_nontemporal_store(a5, &dst[K::pidx(4 * P + v, pc)]);
       if (DELTA) {
         const T b1 = s_ex[ps][0][v][tid], b2 = s_ex[ps][1][v][tid];
         T lo_new;
         Un[v] = K::advance(c_rest[v], ((a1 - b1) + (a2 - b2)) + ((a4 - c4[v]) + (a5 - c5[v])), c_lo[v], lo_new);
-        if (K::COMP) __builtin_nontemporal_store(lo_new, &dst[K::pidx(Q * P + v, cell)]);
+        if (K::COMP) __builtin_nontemporal_store(lo_new, &dst[K::pidx(Q * P + v, pc)]);
       } else {
         Un[v] = ((((T(0) + a1) + a2) + c_rest[v]) + a4) + a5;
       }
-      __builtin_nontemporal_store(DELTA ? Un[v] : c_rest[v], &dst[K::pidx(REST * P + v, cell)]);
+      __builtin_nontemporal_store(DELTA ? Un[v] : c_rest[v], &dst[K::pidx(REST * P + v, pc)]);
     }
     K::new_state(sd, Un, cell, n + 1, lam, cfm);
   };
@@ -997,13 +1003,13 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
         const int hx = map_index(side == 0 ? x0 - 1 : x0 + W, nx, sd.bcx);
         if (PARTIAL) {
           T hU[P], hq[P], hs[P];
-          K::load_one(src, row * nx + hx, side, hU, hq);
+          K::load_one(src, row * rs + hx, side, hU, hq);
           K::template relax_one<0>(hU, hq, side == 0, sd.ph, ixi, Lam, ch, hs);
 #pragma unroll
           for (int v = 0; v < P; ++v) s_halo[buf][side][tid & 31][v] = hs[v];
         } else {
           T hf[Q][P], hU[P];
-          K::collide(src, row * nx + hx, sd.ph, ixi, Lam, ch, hf, hU);
+          K::collide(src, row * rs + hx, sd.ph, ixi, Lam, ch, hf, hU);
 #pragma unroll
           for (int v = 0; v < P; ++v) s_halo[buf][side][tid & 31][v] = side == 0 ? hf[0][v] : hf[1][v];
         }
@@ -1017,13 +1023,13 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
       T(&dstf)[Q][P] = AHEAD == 2 ? fnext2 : fnext;
       T(&dstl)[P] = AHEAD == 2 ? lonext2 : lonext;
       if (k < nr) {
-        K::load_stream(src, row_of(k) * nx + xl, dstf, dstl);
+        K::load_stream(src, row_of(k) * rs + xl, dstf, dstl);
       } else if (k == nr) {
         if (PARTIAL) K::load_one(src, post, qpost, dstf[REST], dstf[PS]);
         else K::load(src, post, dstf);
       }
     } else if (i > 0) {
-      K::load_stream(src, r * nx + xl, fraw, lo);
+      K::load_stream(src, r * rs + xl, fraw, lo);
     }
     K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
     const int slot = (ALTERNATE ? i : r) % 3;
@@ -1111,6 +1117,7 @@ __device__ inline void step2d_tile_axes(const SolveDesc& sd, int tile) {
   constexpr int P = K::P, Q = 5, REST = 2;
   __shared__ double red[2 * (W / 64) + 2], red_end[2 * (W / 64) + 2];
   const int nx = sd.nx, ny = sd.ny, H = sd.band;
+  const long long rs = sd.sx;  // row stride of the population buffers
   const int nsx = (nx + W - 1) / W;
   const int sx = tile % nsx, sy = tile / nsx;
   const int x0 = sx * W, y0 = sy * H, y1 = min(y0 + H, ny), nr = y1 - y0;
@@ -1123,8 +1130,8 @@ __device__ inline void step2d_tile_axes(const SolveDesc& sd, int tile) {
   const StateIn in = read_state(sd);
   const int bp = predicted_parity(sd);
   const gmem<T>* __restrict__ src = gl((const T*)(bp ? sd.fb : sd.fa));
-  const long long below = (long long)map_index(y0 - 1, ny, sd.bcy) * nx + xl;
-  const long long above = (long long)map_index(y1, ny, sd.bcy) * nx + xl;
+  const long long below = (long long)map_index(y0 - 1, ny, sd.bcy) * rs + xl;
+  const long long above = (long long)map_index(y1, ny, sd.bcy) * rs + xl;
   const long long pre = down ? above : below, post = down ? below : above;
   const int qpre = down ? 4 : 3, qpost = down ? 3 : 4;
   // the row before the band (U and its population into the first row); the
@@ -1133,7 +1140,7 @@ __device__ inline void step2d_tile_axes(const SolveDesc& sd, int tile) {
   T preU[P], preq[P], rU[P], rlo[P], ry3[P], ry4[P], rx0[P], rx1[P];
   T nU[P], nlo[P], ny3[P], ny4[P], nx0[P], nx1[P];
   auto load_next = [&](int i) {
-    const long long cell = (long long)row_of(i) * nx + xl;
+    const long long cell = (long long)row_of(i) * rs + xl;
     K::load_slot_stream(src, cell, REST, nU);
     if (K::COMP) K::load_slot_stream(src, cell, Q, nlo);
     K::load_slot_stream(src, cell, 3, ny3);
@@ -1184,7 +1191,7 @@ __device__ inline void step2d_tile_axes(const SolveDesc& sd, int tile) {
     const int hx = map_index(side == 0 ? x0 - 1 : x0 + W, nx, sd.bcx);
     for (int k = tid & 31; k < nr; k += 32) {
       T hU[P], hq[P], hs[P];
-      K::load_one(src, (long long)row_of(k) * nx + hx, side, hU, hq);
+      K::load_one(src, (long long)row_of(k) * rs + hx, side, hU, hq);
       K::template relax_one<0>(hU, hq, side == 0, sd.ph, ixi, Lam, ch, hs);
 #pragma unroll
       for (int v = 0; v < P; ++v) s_halo[side][k][v] = hs[v];
@@ -1203,7 +1210,8 @@ __device__ inline void step2d_tile_axes(const SolveDesc& sd, int tile) {
   auto finish = [&](int j, const T (&ym)[P]) {
     const int rr = row_of(j);
     const int ps = j & 1;
-    const long long cell = (long long)rr * nx + x;
+    const long long cell = (long long)rr * nx + x;  // reported for a non-physical state
+    const long long pc = (long long)rr * rs + x;    // in the population buffers
     T Un[P];
 #pragma unroll
     for (int v = 0; v < P; ++v) {
@@ -1211,15 +1219,15 @@ __device__ inline void step2d_tile_axes(const SolveDesc& sd, int tile) {
       const T a2 = tid < W - 1 ? s_ex[ps][1][v][tid + 1] : s_halo[1][j][v];
       const T a4 = down ? ym[v] : prevm[v];
       const T a5 = down ? prevm[v] : ym[v];
-      __builtin_nontemporal_store(a1, &dst[K::pidx(0 * P + v, cell)]);
-      __builtin_nontemporal_store(a2, &dst[K::pidx(1 * P + v, cell)]);
-      __builtin_nontemporal_store(a4, &dst[K::pidx(3 * P + v, cell)]);
-      __builtin_nontemporal_store(a5, &dst[K::pidx(4 * P + v, cell)]);
+      __builtin_nontemporal_store(a1, &dst[K::pidx(0 * P + v, pc)]);
+      __builtin_nontemporal_store(a2, &dst[K::pidx(1 * P + v, pc)]);
+      __builtin_nontemporal_store(a4, &dst[K::pidx(3 * P + v, pc)]);
+      __builtin_nontemporal_store(a5, &dst[K::pidx(4 * P + v, pc)]);
       const T b1 = s_ex[ps][0][v][tid], b2 = s_ex[ps][1][v][tid];
       T lo_new;
       Un[v] = K::advance(c_rest[v], ((a1 - b1) + (a2 - b2)) + ((a4 - c4[v]) + (a5 - c5[v])), c_lo[v], lo_new);
-      if (K::COMP) __builtin_nontemporal_store(lo_new, &dst[K::pidx(Q * P + v, cell)]);
-      __builtin_nontemporal_store(Un[v], &dst[K::pidx(REST * P + v, cell)]);
+      if (K::COMP) __builtin_nontemporal_store(lo_new, &dst[K::pidx(Q * P + v, pc)]);
+      __builtin_nontemporal_store(Un[v], &dst[K::pidx(REST * P + v, pc)]);
     }
     K::new_state(sd, Un, cell, n + 1, lam, cfm);
   };
@@ -1370,6 +1378,11 @@ __global__ void __launch_bounds__(256) k_init_reduce(const SolveDesc sd) {
   }
 }
 
+// Population-buffer index of natural cell c = j * nx + i (2D rows padded to sx).
+__device__ inline long long pcell(const SolveDesc& sd, long long c) {
+  return sd.sx == sd.nx ? c : (c / sd.nx) * sd.sx + c % sd.nx;
+}
+
 template <int KIND, int DIM, class T, int BASIS>
 __global__ void __launch_bounds__(256) k_init_feq(const SolveDesc sd) {
   using K = Kern<KIND, DIM, T, BASIS>;
@@ -1388,15 +1401,16 @@ __global__ void __launch_bounds__(256) k_init_feq(const SolveDesc sd) {
     for (int v = 0; v < P; ++v) { U[v] = T(sd.stage[v * cells + c]); Us[v] = ST(U[v]); }
     ST fe[Q][P];
     Equilibrium<KIND, DIM, ST>::eval(Us, sd.ph, ST(ixi), ST(S.lam), ST(S.ch), fe);
+    const long long pc = pcell(sd, c);
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
       for (int v = 0; v < P; ++v)
-        f[K::pidx(q * P + v, c)] = (DELTA && q == K::REST) ? U[v] : T(fe[q][v]);
+        f[K::pidx(q * P + v, pc)] = (DELTA && q == K::REST) ? U[v] : T(fe[q][v]);
     if (K::COMP) {
 #pragma unroll
       for (int v = 0; v < P; ++v)
-        f[K::pidx(Q * P + v, c)] = T(sd.stage[v * cells + c] - double(U[v]));
+        f[K::pidx(Q * P + v, pc)] = T(sd.stage[v * cells + c] - double(U[v]));
     }
   }
 }
@@ -1412,17 +1426,18 @@ __global__ void __launch_bounds__(256) k_moments(const SolveDesc sd) {
   double* out = const_cast<double*>(sd.stage);
   const long long cells = (long long)sd.nx * sd.ny;
   for (long long c = blockIdx.x * 256ll + threadIdx.x; c < cells; c += (long long)gridDim.x * 256) {
+    const long long pc = pcell(sd, c);
 #pragma unroll
     for (int v = 0; v < P; ++v) {
       T s;
       if (DELTA) {
-        s = f[K::pidx(K::REST * P + v, c)];
+        s = f[K::pidx(K::REST * P + v, pc)];
       } else {
         s = T(0);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) s += f[K::pidx(q * P + v, c)];
+        for (int q = 0; q < Q; ++q) s += f[K::pidx(q * P + v, pc)];
       }
-      out[v * cells + c] = K::COMP ? double(s) + double(f[K::pidx(Q * P + v, c)]) : double(s);
+      out[v * cells + c] = K::COMP ? double(s) + double(f[K::pidx(Q * P + v, pc)]) : double(s);
     }
   }
 }
