@@ -212,11 +212,9 @@ std::mutex g_tiles_mu;
 std::map<std::array<int, 4>, std::pair<int, int>> g_tiles;
 
 // Band and halo heights for a 2D solve of this kind and side: the tuned entry
-// of its size class, else the nearest tuned class of the kind, else the
-// single-solve defaults.
+// of its size class, else the nearest tuned class of the kind, else (no tuned
+// entry) *band and *halo as given.
 void pick_shape(const vklb_pool* p, int kind, long long n, int* band, int* halo) {
-  *band = default_band(kind);
-  *halo = default_halo(kind);
   const int want = size_class(n);
   int bestd = 1 << 30;
   std::lock_guard<std::mutex> lk(g_tiles_mu);
@@ -400,7 +398,7 @@ vklb_status vklb_pool_submit(vklb_pool* p, const vklb_request* rq, uint64_t* tic
   r->U0.assign(rq->U0, rq->U0 + size_t(r->L.p) * cells);
   r->U_out = rq->U_out;
   r->cls = class_of(r->sys.kind, r->grid.dim);
-  r->band = default_band(r->sys.kind);
+  r->band = r->grid.dim == 2 ? default_band(&r->grid, 128) : 32;  // the batched 2D strips are 128 columns
   r->halo = default_halo(r->sys.kind);
   if (r->grid.dim == 2) pick_shape(p, r->sys.kind, r->grid.n[0], &r->band, &r->halo);
   r->band = std::min(r->band, max_band(r->sys.kind, r->grid.dim, p->basis[r->grid.dim]));

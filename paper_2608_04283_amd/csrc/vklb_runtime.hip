@@ -409,7 +409,7 @@ vklb_status plan_solve(const vklb_system* sys, vklb_lattice lat, const vklb_grid
   pl->width = width;
   pl->K = pick_launchers(sys->kind, grid->dim, prec == VKLB_FP32 ? 1 : 0, pl->basis, width);
   int band = o.band_rows;
-  if (band < 1) band = default_band(sys->kind);
+  if (band < 1) band = default_band(grid, width);
   if (band > max_band(sys->kind, grid->dim, pl->basis)) band = max_band(sys->kind, grid->dim, pl->basis);
   pl->band = band;
   int halo = o.halo_rows;
