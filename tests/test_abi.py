@@ -137,6 +137,21 @@ def test_size_limits(vk):
     assert b >= 2 * 6 * 4 * cells * 4   # two buffers of (Q + 1) * p FP32 planes
 
 
+def test_2d_rows_padded_to_64_cells(vk):
+    """2D population buffers hold each row in a multiple of 64 cells (so a
+    wavefront's row segment is one aligned run whatever the side), while the
+    FP64 staging of U keeps the natural nx * ny cells: a 65-column grid needs
+    the population bytes of a 128-column one."""
+    Q = I.quadrants(16, steps=1)
+    def pop_bytes(nx, ny):
+        b = vk.workspace_bytes(Q.with_(n=(nx, ny), hi=(nx / ny, 1.0)), "fp32")
+        assert b > 0
+        return b - Q.p * nx * ny * 8          # minus the FP64 staging of U
+    assert abs(pop_bytes(65, 64) - pop_bytes(128, 64)) <= 4096
+    assert pop_bytes(65, 64) > pop_bytes(64, 64) + 2 * 20 * 63 * 64 * 4 - 4096
+    assert abs(pop_bytes(64, 64) - pop_bytes(1, 64)) <= 4096    # one column pads to 64
+
+
 def test_lattice_grid_mismatch_and_dx_dy(vk):
     r, msg = create(vk, I.sod(100), lat=1)
     assert r == vk.ERR_ARG and "lattice" in msg
