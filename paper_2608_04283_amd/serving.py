@@ -81,10 +81,12 @@ def _alg_bytes(prob, precision):
     return 2 * prob.Q * prob.p * (4 if precision == "fp32" else 8)
 
 
-def run_batched(requests, budget_bytes, precision="fp32", chunk_rounds=32, realtime=True, keep_results=False,
+def run_batched(requests, budget_bytes, precision="fp32", chunk_rounds=64, realtime=True, keep_results=False,
                 progress=None):
-    """Serve `requests` (inputs.Request, sorted by arrival) through a pool;
-    progress(done, total) is called after every 200th completion."""
+    """Serve `requests` (inputs.Request, sorted by arrival) through a pool,
+    `chunk_rounds` rounds per vklb_pool_run between polls (64 measured best
+    on the seed-1 stream: 2 % more capacity than 32 and no worse latency at
+    80 % load); progress(done, total) is called after every 200th completion."""
     reqs = sorted(requests, key=lambda r: r.arrival)
     pool = vklb.Pool(budget_bytes, precision)
     pre = _Prefetch(reqs)
