@@ -193,6 +193,26 @@ inline hipError_t launch_fold(const SolveDesc& d, int par, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Checkpoint blobs hold the populations with their rows in grid order, so a
+// blob does not depend on the band height of the solver that wrote it. Copy a
+// population buffer between that order and the device's (mem_row; to_grid:
+// device to grid order), in runs of 64 cells, which never cross a 256-cell
+// block since rows are padded to a multiple of 64 cells.
+inline void reorder_rows(const char* from, char* to, const SolveDesc& d, const Layout& L, bool down_odd, bool to_grid) {
+  const size_t planes = size_t(L.slots) * L.p, run = size_t(64) * L.elem;
+  auto off = [&](long long cell, size_t plane) {
+    return ((size_t(cell) >> kBlockLog2) * planes + plane) * kBlock * L.elem + size_t(cell & (kBlock - 1)) * L.elem;
+  };
+  for (int r = 0; r < d.ny; ++r) {
+    const long long m = mem_row(r, d.band, d.nfull, down_odd);
+    for (long long x = 0; x < d.sx; x += 64) {
+      const long long gc = (long long)r * d.sx + x, mc = m * d.sx + x;
+      for (size_t pl = 0; pl < planes; ++pl)
+        memcpy(to + off(to_grid ? gc : mc, pl), from + off(to_grid ? mc : gc, pl), run);
+    }
+  }
+}
+
 // Kernel descriptor of a solve whose workspace starts at `base`.
 inline SolveDesc make_desc(char* base, const Layout& L, const vklb_system* sys, const vklb_grid* grid,
                            const vklb_speed* lambda, double omega, const vklb_bc bc[2], const vklb_equilibrium* eq,
@@ -235,6 +255,7 @@ inline SolveDesc make_desc(char* base, const Layout& L, const vklb_system* sys, 
   d.bcx = bc[0] == VKLB_BC_PERIODIC ? 0 : (bc[0] == VKLB_BC_CHARACTERISTIC ? 2 : 1);
   d.bcy = (grid->dim == 2 ? bc[1] : bc[0]) == VKLB_BC_PERIODIC ? 0 : 1;
   d.band = band;
+  d.nfull = grid->dim == 2 && band > 0 ? int(d.ny / band) : 0;
   d.halo = halo;
   d.nblocks = step_grid_of(grid, width, band);
   d.nred = d.nblocks;

@@ -8,7 +8,10 @@
 // (plane = slot * P + var, 256 values each): structure of arrays inside a
 // block, so every load and store of a wavefront is one contiguous 256-byte
 // (FP32) run and a workgroup row touches one region, not Q * P far-apart
-// streams. Two population buffers ping-pong by step parity. In the "delta" basis the
+// streams. In 2D the rows of the whole bands are stored interleaved in march
+// order (mem_row below), so that the bands of a launch, which march in step,
+// work in one compact stretch of the buffers at a time rather than in as many
+// stretches as there are bands. Two population buffers ping-pong by step parity. In the "delta" basis the
 // rest-population plane holds U instead (the rest population is U minus the
 // moving ones), which keeps FP32 rounding relative to the small per-step
 // change of U rather than to U itself.
@@ -73,12 +76,25 @@ struct SolveDesc {
   int bcx, bcy;          // 0 periodic, 1 zero gradient
   int nblocks;           // workgroups per step launch (= number of partials)
   int band;              // 2D rows per band
+  int nfull;             // 2D: whole bands (ny / band), whose rows are stored interleaved (mem_row)
   int par;               // launch parity
   int halo;              // 2D rows of halo columns collided per batch (1..32)
   int npar;              // parity of the step index at launches of parity 0
   int nred;              // partials a step launch reduces at entry: nblocks, or 1 when
                          // each launch's partials are folded into entry 0 after it
 };
+
+// Row of the population buffers that holds grid row r (2D). March step i of
+// whole band b sits at row i * nfull + b: the bands of one launch advance
+// together, so at any time they read and write neighbouring rows of the
+// buffers. Bands that march down (odd MHD bands) count their steps from the
+// top. The rows of a last, partial band keep their place. With nfull = 0 the
+// rows are in grid order. The map is a permutation of the ny rows.
+__host__ __device__ inline long long mem_row(int r, int band, int nfull, bool down_odd) {
+  if (r >= nfull * band) return r;
+  const int b = r / band, i = r - b * band;
+  return (long long)((down_odd && (b & 1)) ? band - 1 - i : i) * nfull + b;
+}
 
 // Global-memory views of a solve's device pointers. The single-solve kernels
 // take the descriptor as a kernel argument, whose pointers the compiler
@@ -876,6 +892,9 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
   constexpr bool ALTERNATE = KIND == K_MHD;
   const bool down = ALTERNATE && (sy & 1) != 0;
   auto row_of = [&](int i) { return down ? y1 - 1 - i : y0 + i; };
+  // Row of the population buffers that holds march index i (mem_row).
+  const bool whole = sy < sd.nfull;
+  auto mem_of = [&](int i) -> long long { return whole ? (long long)i * sd.nfull + sy : row_of(i); };
   const StateIn in = read_state(sd);
   const int bp = predicted_parity(sd);
   const gmem<T>* __restrict__ src = gl((const T*)(bp ? sd.fb : sd.fa));
@@ -892,8 +911,8 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
   constexpr bool PARTIAL = DELTA;
   // The row before the band in march order streams one population into its
   // first row (y0 - 1: +y up; y1: -y down); the row after it, into its last.
-  const long long below = (long long)map_index(y0 - 1, ny, sd.bcy) * rs + xl;
-  const long long above = (long long)map_index(y1, ny, sd.bcy) * rs + xl;
+  const long long below = mem_row(map_index(y0 - 1, ny, sd.bcy), H, sd.nfull, ALTERNATE) * rs + xl;
+  const long long above = mem_row(map_index(y1, ny, sd.bcy), H, sd.nfull, ALTERNATE) * rs + xl;
   const long long pre = down ? above : below, post = down ? below : above;
   const int qpre = down ? 4 : 3, qpost = down ? 3 : 4;
   // Array slot that receives the row after the band's population (fixed, so
@@ -905,11 +924,11 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
   auto load_first = [&]() {
     if (PARTIAL) K::load_one(src, pre, qpre, fpre[REST], fpre[3]);
     else K::load(src, pre, fpre);
-    K::load_stream(src, row_of(0) * rs + xl, fraw, lo);
+    K::load_stream(src, mem_of(0) * rs + xl, fraw, lo);
     if (AHEAD == 2) {
       // the second row (or, in a one-row band, the row after the band)
       if (nr > 1) {
-        K::load_stream(src, row_of(1) * rs + xl, fnext, lonext);
+        K::load_stream(src, mem_of(1) * rs + xl, fnext, lonext);
       } else {
         if (PARTIAL) K::load_one(src, post, qpost, fnext[REST], fnext[PS]);
         else K::load(src, post, fnext);
@@ -966,7 +985,7 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
     const int rb = j / hb;
     const int hbuf = rb % 3, hr = j - rb * hb;
     const long long cell = (long long)rr * nx + x;  // reported for a non-physical state
-    const long long pc = (long long)rr * rs + x;    // in the population buffers
+    const long long pc = mem_of(j) * rs + x;        // in the population buffers
     T Un[P];
 #pragma unroll
     for (int v = 0; v < P; ++v) {
@@ -999,17 +1018,17 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
       const int side = tid >> 5;
       const int k = i + (tid & 31);
       if ((tid & 31) < hb && k < nr) {
-        const int row = row_of(k);
+        const long long hrow = mem_of(k) * rs;
         const int hx = map_index(side == 0 ? x0 - 1 : x0 + W, nx, sd.bcx);
         if (PARTIAL) {
           T hU[P], hq[P], hs[P];
-          K::load_one(src, row * rs + hx, side, hU, hq);
+          K::load_one(src, hrow + hx, side, hU, hq);
           K::template relax_one<0>(hU, hq, side == 0, sd.ph, ixi, Lam, ch, hs);
 #pragma unroll
           for (int v = 0; v < P; ++v) s_halo[buf][side][tid & 31][v] = hs[v];
         } else {
           T hf[Q][P], hU[P];
-          K::collide(src, row * rs + hx, sd.ph, ixi, Lam, ch, hf, hU);
+          K::collide(src, hrow + hx, sd.ph, ixi, Lam, ch, hf, hU);
 #pragma unroll
           for (int v = 0; v < P; ++v) s_halo[buf][side][tid & 31][v] = side == 0 ? hf[0][v] : hf[1][v];
         }
@@ -1024,14 +1043,14 @@ __device__ inline void step2d_tile_rows(const SolveDesc& sd, int tile) {
       T(&dstl)[P] = AHEAD == 2 ? lonext2 : lonext;
       if (k < nr) {
         __builtin_amdgcn_s_setprio(2);  // prefetch at raised wave priority, as in step2d_tile_axes
-        K::load_stream(src, row_of(k) * rs + xl, dstf, dstl);
+        K::load_stream(src, mem_of(k) * rs + xl, dstf, dstl);
         __builtin_amdgcn_s_setprio(0);
       } else if (k == nr) {
         if (PARTIAL) K::load_one(src, post, qpost, dstf[REST], dstf[PS]);
         else K::load(src, post, dstf);
       }
     } else if (i > 0) {
-      K::load_stream(src, r * rs + xl, fraw, lo);
+      K::load_stream(src, mem_of(i) * rs + xl, fraw, lo);
     }
     K::relax(fraw, sd.ph, ixi, Lam, ch, fs, U);
     const int slot = (ALTERNATE ? i : r) % 3;
@@ -1129,11 +1148,14 @@ __device__ inline void step2d_tile_axes(const SolveDesc& sd, int tile) {
   // bands march up (even sy) or down (odd sy), as in step2d_tile_rows
   const bool down = (sy & 1) != 0;
   auto row_of = [&](int i) { return down ? y1 - 1 - i : y0 + i; };
+  // Row of the population buffers that holds march index i (mem_row).
+  const bool whole = sy < sd.nfull;
+  auto mem_of = [&](int i) -> long long { return whole ? (long long)i * sd.nfull + sy : row_of(i); };
   const StateIn in = read_state(sd);
   const int bp = predicted_parity(sd);
   const gmem<T>* __restrict__ src = gl((const T*)(bp ? sd.fb : sd.fa));
-  const long long below = (long long)map_index(y0 - 1, ny, sd.bcy) * rs + xl;
-  const long long above = (long long)map_index(y1, ny, sd.bcy) * rs + xl;
+  const long long below = mem_row(map_index(y0 - 1, ny, sd.bcy), H, sd.nfull, true) * rs + xl;
+  const long long above = mem_row(map_index(y1, ny, sd.bcy), H, sd.nfull, true) * rs + xl;
   const long long pre = down ? above : below, post = down ? below : above;
   const int qpre = down ? 4 : 3, qpost = down ? 3 : 4;
   // the row before the band (U and its population into the first row); the
@@ -1142,7 +1164,7 @@ __device__ inline void step2d_tile_axes(const SolveDesc& sd, int tile) {
   T preU[P], preq[P], rU[P], rlo[P], ry3[P], ry4[P], rx0[P], rx1[P];
   T nU[P], nlo[P], ny3[P], ny4[P], nx0[P], nx1[P];
   auto load_next = [&](int i) {
-    const long long cell = (long long)row_of(i) * rs + xl;
+    const long long cell = mem_of(i) * rs + xl;
     K::load_slot_stream(src, cell, REST, nU);
     if (K::COMP) K::load_slot_stream(src, cell, Q, nlo);
     K::load_slot_stream(src, cell, 3, ny3);
@@ -1193,7 +1215,7 @@ __device__ inline void step2d_tile_axes(const SolveDesc& sd, int tile) {
     const int hx = map_index(side == 0 ? x0 - 1 : x0 + W, nx, sd.bcx);
     for (int k = tid & 31; k < nr; k += 32) {
       T hU[P], hq[P], hs[P];
-      K::load_one(src, (long long)row_of(k) * rs + hx, side, hU, hq);
+      K::load_one(src, mem_of(k) * rs + hx, side, hU, hq);
       K::template relax_one<0>(hU, hq, side == 0, sd.ph, ixi, Lam, ch, hs);
 #pragma unroll
       for (int v = 0; v < P; ++v) s_halo[side][k][v] = hs[v];
@@ -1213,7 +1235,7 @@ __device__ inline void step2d_tile_axes(const SolveDesc& sd, int tile) {
     const int rr = row_of(j);
     const int ps = j & 1;
     const long long cell = (long long)rr * nx + x;  // reported for a non-physical state
-    const long long pc = (long long)rr * rs + x;    // in the population buffers
+    const long long pc = mem_of(j) * rs + x;        // in the population buffers
     T Un[P];
 #pragma unroll
     for (int v = 0; v < P; ++v) {
@@ -1385,9 +1407,12 @@ __global__ void __launch_bounds__(256) k_init_reduce(const SolveDesc sd) {
   }
 }
 
-// Population-buffer index of natural cell c = j * nx + i (2D rows padded to sx).
-__device__ inline long long pcell(const SolveDesc& sd, long long c) {
-  return sd.sx == sd.nx ? c : (c / sd.nx) * sd.sx + c % sd.nx;
+// Population-buffer index of natural cell c = j * nx + i (2D: rows padded to
+// sx and placed by mem_row; down_odd: the solve's odd bands march down).
+__device__ inline long long pcell(const SolveDesc& sd, long long c, bool down_odd) {
+  if (sd.sx == sd.nx && sd.nfull == 0) return c;
+  const long long j = c / sd.nx;
+  return mem_row(int(j), sd.band, sd.nfull, down_odd) * sd.sx + (c - j * sd.nx);
 }
 
 template <int KIND, int DIM, class T, int BASIS>
@@ -1408,7 +1433,7 @@ __global__ void __launch_bounds__(256) k_init_feq(const SolveDesc sd) {
     for (int v = 0; v < P; ++v) { U[v] = T(sd.stage[v * cells + c]); Us[v] = ST(U[v]); }
     ST fe[Q][P];
     Equilibrium<KIND, DIM, ST>::eval(Us, sd.ph, ST(ixi), ST(S.lam), ST(S.ch), fe);
-    const long long pc = pcell(sd, c);
+    const long long pc = pcell(sd, c, KIND == K_MHD);
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -1433,7 +1458,7 @@ __global__ void __launch_bounds__(256) k_moments(const SolveDesc sd) {
   double* out = const_cast<double*>(sd.stage);
   const long long cells = (long long)sd.nx * sd.ny;
   for (long long c = blockIdx.x * 256ll + threadIdx.x; c < cells; c += (long long)gridDim.x * 256) {
-    const long long pc = pcell(sd, c);
+    const long long pc = pcell(sd, c, KIND == K_MHD);
 #pragma unroll
     for (int v = 0; v < P; ++v) {
       T s;

@@ -705,6 +705,10 @@ vklb_status vklb_get_state(vklb_solver* s, void* host, double* t, int64_t* steps
   const char* src = (v.S.n & 1) ? static_cast<const char*>(s->sd.fb) : static_cast<const char*>(s->sd.fa);
   HIPCHK(s, hipMemcpyAsync(host, src, pop, hipMemcpyDeviceToHost, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
+  if (s->sd.nfull > 1) {  // rows to grid order
+    std::vector<char> dev(static_cast<const char*>(host), static_cast<const char*>(host) + pop);
+    reorder_rows(dev.data(), static_cast<char*>(host), s->sd, s->L, s->sys.kind == VKLB_MHD_GLM, true);
+  }
   CkptTrailer tr = make_trailer(s);
   tr.t = v.S.t;
   tr.n = v.S.n;
@@ -728,7 +732,14 @@ vklb_status vklb_set_state(vklb_solver* s, const void* host) {
       tr.basis != me.basis || tr.nx != me.nx || tr.ny != me.ny || tr.n < 0)
     return fail(s, VKLB_ERR_ARG, "checkpoint does not belong to a solver of this shape");
   char* dst = (tr.n & 1) ? static_cast<char*>(s->sd.fb) : static_cast<char*>(s->sd.fa);
-  HIPCHK(s, hipMemcpyAsync(dst, host, pop, hipMemcpyHostToDevice, s->stream));
+  if (s->sd.nfull > 1) {  // rows to the device's order
+    std::vector<char> dev(pop, 0);
+    reorder_rows(static_cast<const char*>(host), dev.data(), s->sd, s->L, s->sys.kind == VKLB_MHD_GLM, false);
+    HIPCHK(s, hipMemcpyAsync(dst, dev.data(), pop, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+  } else {
+    HIPCHK(s, hipMemcpyAsync(dst, host, pop, hipMemcpyHostToDevice, s->stream));
+  }
   vklb_status st = reset_state(s, tr.t, tr.n, tr.done);
   if (st != VKLB_OK) return st;
   // The saved maxima stand in for the partials of parity 0 (the max is exact).
