@@ -214,8 +214,9 @@ vklb_status vklb_progress(vklb_solver* s, double* t, int64_t* steps, int* done);
 vklb_status vklb_diagnostics(vklb_solver* s, vklb_diag* d);
 
 /* Checkpoint / resume. The blob (vklb_state_bytes bytes) holds the stored
- * populations in the device layout (blocks of 256 cells, each holding its
- * [slot][var][256] values; the solver's precision and basis)
+ * populations in the device's block layout (blocks of 256 cells, each holding its
+ * [slot][var][256] values; the solver's precision and basis; 2D rows padded to a
+ * multiple of 64 cells) with the rows in grid order, whatever the band height,
  * followed by a 128-byte trailer with t, the step count, xi, Lambda, c_h, the
  * end-time landing flag and the solve's shape. vklb_set_state restores all of
  * it, so a resumed run continues bit for bit; it rejects (VKLB_ERR_ARG) a blob
