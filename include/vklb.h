@@ -134,8 +134,8 @@ typedef struct {
                        0: default: FP64 -> 1; FP32 -> 3 in 1D, 2 in 2D.
                        Other values: VKLB_ERR_ARG. */
   int band_rows;    /* 2D: rows per workgroup band (MHD in the delta bases: at most 64, larger values
-                       are taken as 64); 0 = the default: the tallest of 32, 16, 8 and 4 rows that
-                       gives a step at least 2048 wavefronts (two per SIMD) */
+                       are taken as 64); 0 = the default: the tallest power of two from 512 down to
+                       4 rows that gives a step at least 2048 wavefronts (two per SIMD) */
   int graph_chunk;  /* steps captured per HIP graph (0 = 512; < 0: plain launches) */
   int strip_width;  /* 2D: columns per workgroup (64, 128 or 256); 1D: lanes per workgroup
                        (256 or 512, each finishing W - 2 cells); 0 = tuned default */

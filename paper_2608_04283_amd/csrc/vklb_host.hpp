@@ -107,20 +107,22 @@ inline int default_width(int dim, long long nx) {
   return nx <= 64 ? 64 : (nx <= 128 ? 128 : 256);
 }
 // Rows per 2D band for strips of `width` columns (width / 64 wavefronts per
-// workgroup): the tallest power of two from 32 down to 4 that still gives the
+// workgroup): the tallest power of two from 512 down to 4 that still gives the
 // step at least 2048 wavefronts (two per SIMD, the most the MHD march's
-// registers allow), so a mid-size grid does not leave SIMDs idle while a
-// large one keeps long bands (fewer halo and edge-row reads per cell).
-// Measured on MI355X (FP32, 256-column strips, us per step): 2D Euler 1024^2
-// 33.2 with 8 rows against 56.4 with 32, 512^2 12.5 (4 rows) against 55.2;
-// shallow water 1024^2 26.0 (8) against 45.9; MHD 512^2 37.6 (4) against
-// 59.2 (8), 2048^2 309 (32) against 321 (8); Euler 2048^2 and MHD 1024^2
-// keep 32 and 8. MHD 1024^2 in 128-column strips: 16-row bands (one wave per
-// SIMD) 126.9 us, 8-row bands 88.
+// registers allow). A mid-size grid then does not leave SIMDs idle, and a
+// large one runs its workgroups in one wave with few halo and edge-row reads
+// per cell. Measured on MI355X (FP32, 256-column strips, us per step): 2D
+// Euler 1024^2 33.2 with 8 rows against 56.4 with 32, 512^2 12.5 (4 rows)
+// against 55.2; shallow water 1024^2 26.0 (8) against 45.9; MHD 512^2 37.6
+// (4) against 59.2 (8), 2048^2 309 (32) against 321 (8); Euler 2048^2 and MHD
+// 1024^2 keep 32 and 8. With the rows of whole bands interleaved: Euler
+// 4096^2 472 (128 rows) against 529 (32), 8192^2 2017 (512) against 2082
+// (32); shallow water 4096^2 354 (128) against 389 (32). MHD 1024^2 in
+// 128-column strips: 16-row bands (one wave per SIMD) 126.9 us, 8-row 88.
 inline int default_band(const vklb_grid* g, int width) {
   const long long strips = (g->n[0] + width - 1) / width, ny = g->dim == 2 ? g->n[1] : 1;
   const long long waves_per_group = (width + 63) / 64;
-  int band = 32;
+  int band = 512;
   while (band > 4 && strips * ((ny + band - 1) / band) * waves_per_group < 2048) band /= 2;
   return band;
 }

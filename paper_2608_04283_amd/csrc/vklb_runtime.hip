@@ -803,7 +803,11 @@ static vklb_status tune_impl(const vklb_system* sys, vklb_lattice lat, const vkl
     const long long nx = grid->n[0], ny = grid->n[1];
     for (int w : {64, 128, 256}) {
       if (w > 64 && (nx + w - 1) / w * w - nx >= w / 2) continue;  // mostly idle lanes
-      for (int band : {4, 8, 16, 32, 64}) {
+      // the default rule's band too, where it is taller than these (large grids)
+      std::vector<int> bands = {4, 8, 16, 32, 64};
+      const int rule = std::min(default_band(grid, w), max_band(sys->kind, 2, resolve_basis(b0.basis, prec, 2)));
+      if (rule > 64) bands.push_back(rule);
+      for (int band : bands) {
         if (band > 4 && band / 2 >= ny) continue;
         for (int halo : {2, 8, 16, 32}) {
           if (halo > band) continue;
