@@ -1,7 +1,10 @@
-// Host-side evaluation of the per-cell arithmetic in vklb_cell.hpp, for the
-// CPU test suite only (it lets the closed-form splits be compared with the
-// oracle without a GPU). Nothing in the library's entry points calls it.
+// Host-side evaluation of the per-cell arithmetic in vklb_cell.hpp, and of
+// the 2D row placement of the population buffers (mem_row, reorder_rows in
+// vklb_host.hpp), for the CPU test suite only (it lets the closed-form splits
+// be compared with the oracle, and the layout be checked, without a GPU).
+// Nothing in the library's entry points calls it.
 #include "vklb_cell.hpp"
+#include "vklb_host.hpp"
 
 using namespace vklb;
 
@@ -127,5 +130,28 @@ int vklb_cc_feq(int prec, int kind, int dim, const double* U, const double* prm,
 int vklb_cc_speeds(int prec, int kind, int dim, const double* U, const double* prm, double* lam, double* cfm) {
   return prec == 4 ? speeds_any<float>(kind, dim, U, prm, lam, cfm)
                    : speeds_any<double>(kind, dim, U, prm, lam, cfm);
+}
+// Buffer row of grid row r (mem_row) for bands of `band` rows, of which
+// nfull are whole; down_odd: odd bands march down (MHD).
+long long vklb_cc_mem_row(int r, int band, int nfull, int down_odd) { return mem_row(r, band, nfull, down_odd != 0); }
+// reorder_rows over a population buffer of `planes` planes of elem-byte
+// values for a 2D grid of row stride sx (a multiple of 64) and ny rows:
+// to_grid = 1 from the device's row order to grid order, 0 the reverse.
+// `from` and `to` hold stride * planes values, stride = sx * ny rounded up to
+// whole 256-cell blocks.
+void vklb_cc_reorder_rows(const void* from, void* to, int sx, int ny, int band, int nfull, int down_odd, int planes,
+                          int elem, int to_grid) {
+  SolveDesc d;
+  memset(&d, 0, sizeof d);
+  d.sx = sx;
+  d.ny = ny;
+  d.band = band;
+  d.nfull = nfull;
+  Layout L;
+  memset(&L, 0, sizeof L);
+  L.slots = planes;
+  L.p = 1;
+  L.elem = elem;
+  reorder_rows(static_cast<const char*>(from), static_cast<char*>(to), d, L, down_odd != 0, to_grid != 0);
 }
 }
