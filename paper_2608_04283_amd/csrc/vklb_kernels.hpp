@@ -11,10 +11,10 @@
 // streams. In 2D the rows of the whole bands are stored interleaved in march
 // order (mem_row below), so that the bands of a launch, which march in step,
 // work in one compact stretch of the buffers at a time rather than in as many
-// stretches as there are bands. Two population buffers ping-pong by step parity. In the "delta" basis the
-// rest-population plane holds U instead (the rest population is U minus the
-// moving ones), which keeps FP32 rounding relative to the small per-step
-// change of U rather than to U itself.
+// stretches as there are bands. Two population buffers ping-pong by step
+// parity. In the "delta" basis the rest-population plane holds U instead (the
+// rest population is U minus the moving ones), which keeps FP32 rounding
+// relative to the small per-step change of U rather than to U itself.
 //
 // Per-step global quantities (Sec. 3.2 CFL speed, Sec. 5.3 cleaning speed)
 // need the max over every cell of the NEW state. Each workgroup therefore
